@@ -1,0 +1,38 @@
+"""Build the FP64 CPU oracle (test infrastructure) as a shared library.
+
+Plain C, gcc, no fast-math and no FMA contraction, OpenMP over independent
+per-node loops.  The output lands in oracle/_build/liblbm_oracle.so.
+"""
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+OUT_DIR = os.path.join(HERE, "_build")
+LIB = os.path.join(OUT_DIR, "liblbm_oracle.so")
+SOURCES = [os.path.join(HERE, "lbm_oracle.c")]
+
+
+def build(extra_flags=(), out=LIB, verbose=False):
+    """Compile the oracle; returns the library path.  extra_flags lets the
+    mutation tests build deliberately broken copies under another name."""
+    os.makedirs(os.path.dirname(out), exist_ok=True)
+    cmd = ["gcc", "-std=c99", "-O2", "-fPIC", "-shared", "-fopenmp",
+           "-ffp-contract=off", "-fno-fast-math", "-Wall", "-Wextra",
+           *extra_flags, *SOURCES, "-o", out + ".tmp", "-lm"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(out + ".tmp", out)
+    return out
+
+
+def ensure_built():
+    if not os.path.exists(LIB):
+        build()
+    return LIB
+
+
+if __name__ == "__main__":
+    build(verbose=True)
+    sys.exit(0)

@@ -1,0 +1,150 @@
+"""Benchmark of the fused phase-field LBM step on one MI355X.
+
+Workload: droplet splash on a thin film, 1024 x 512 D2Q9, periodic in x,
+bounce-back walls in y, FP32 populations, corrected model (the whole path
+including the lap mu stencil of the -F_a correction).  A step is one lattice
+time step of the whole grid; the default K = 20000 steps is the workload's
+length.  Inputs are resident in HBM before timing starts.
+
+Prints one JSON line: MLUPS (lattice updates per second / 1e6), the roofline
+of the fused step kernel (algorithmic bytes 148 B per lattice update in FP32:
+18 float populations plus the 2-byte low part of f_0, read once and written
+once), the FP64 CPU oracle timed on a
+bounded sample of the same workload, and the same measurements for FP16
+storage (76 B per update) and the original model.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_LU = {"fp32": 148.0, "fp16": 76.0, "bf16": 76.0}
+PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--storage", default="fp32")
+    ap.add_argument("--remove-fa", type=int, default=1)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
+    ap.add_argument("--no-extra", action="store_true", help="skip the FP16 / original-model legs")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    return ap.parse_args()
+
+
+def time_gpu(torch, sim, steps, warmup):
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    sim.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / 1e3
+
+
+def leg(torch, W, hip, storage, remove_fa, steps, warmup):
+    case = W.splash_2d(remove_fa=remove_fa)
+    sim = hip.Simulation([case], storage=storage)
+    t = time_gpu(torch, sim, steps, warmup)
+    d = sim.diagnostics()
+    n = case.n
+    mlups = n * steps / t / 1e6
+    sim.close()
+    return dict(mlups=mlups, seconds=t, ms_per_step=1e3 * t / steps, nodes=n,
+                mass_drift_rel=d["mass_drift_rel"], nonfinite=int(d["nonfinite"]),
+                umax=d["umax"])
+
+
+def cpu_baseline(W, seconds):
+    """The FP64 oracle as it stands on the host cores, on the same workload,
+    stepping until about `seconds` have passed."""
+    from oracle import oracle as O
+    case = W.splash_2d(remove_fa=1)
+    s = O.Sim(case.params, case.phi0, case.u0, case.p0)
+    s.step(1)
+    t0 = time.perf_counter()
+    steps = 0
+    while time.perf_counter() - t0 < seconds:
+        s.step(2)
+        steps += 2
+    dt = time.perf_counter() - t0
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return dict(value=case.n * steps / dt / 1e6, unit="MLUPS", cores=cores, kind="oracle",
+                sample=f"{steps} steps of the 1024x512 splash workload (corrected model), "
+                       f"{dt:.1f} s, FP64")
+
+
+def traffic_for(kernel_key):
+    try:
+        with open(PROFILE_TRAFFIC) as f:
+            return json.load(f).get(kernel_key)
+    except (OSError, ValueError):
+        return None
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+    import torch
+    import paper_1110_5004_amd as hip
+    import workloads as W
+    hip.lib()
+
+    main_leg = leg(torch, W, hip, a.storage, a.remove_fa, a.steps, a.warmup)
+    bpl = BYTES_PER_LU[a.storage]
+    achieved = main_leg["nodes"] * bpl / (main_leg["seconds"] / a.steps) / 1e9
+    key = f"splash1024x512_{a.storage}_rf{a.remove_fa}"
+    out = {
+        "metric": "lattice updates/s (MLUPS), fused D2Q9 phase-field step",
+        "value": round(main_leg["mlups"], 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(main_leg["ms_per_step"], 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if a.storage == "fp32" else f"f32 compute, {a.storage} storage",
+        "data": "synthetic (seeded splash initial condition)",
+        "config": {"workload": "splash1024x512", "grid": [1024, 512], "lattice": "D2Q9",
+                   "bc": "periodic x, walls y", "storage": a.storage,
+                   "remove_fa": a.remove_fa, "steps_in_job": 20000},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic_for(key),
+                     "bytes_per_lu": bpl},
+        "check": {"mass_drift_rel": main_leg["mass_drift_rel"],
+                  "nonfinite": main_leg["nonfinite"], "umax": main_leg["umax"]},
+    }
+    if not a.no_extra:
+        extra = {}
+        for st, rf in (("fp16", a.remove_fa), ("bf16", a.remove_fa), (a.storage, 1 - a.remove_fa)):
+            r = leg(torch, W, hip, st, rf, a.steps, a.warmup)
+            ach = r["nodes"] * BYTES_PER_LU[st] / (r["seconds"] / a.steps) / 1e9
+            extra[f"{st}_rf{rf}"] = dict(mlups=round(r["mlups"], 1),
+                                         achieved_gbs=round(ach, 1),
+                                         frac=round(ach / HBM_PEAK_GBS, 4),
+                                         nonfinite=r["nonfinite"],
+                                         mass_drift_rel=r["mass_drift_rel"])
+        out["variants"] = extra
+    if not a.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(W, a.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,196 @@
+/*
+ * lbm.h -- C ABI of the MI355X (gfx950) phase-field lattice Boltzmann library.
+ *
+ * The library advances the incompressible two-distribution phase-field LB
+ * model analysed by Li, Luo & Gao, "Additional interfacial force in lattice
+ * Boltzmann models for incompressible multiphase flows" (arXiv:1110.5004):
+ *   - order parameter phi with bulk free energy beta phi^2 (phi-1)^2 and
+ *     gradient coefficient kappa (Eq. 1a), chemical potential
+ *     mu = theta'(phi) - kappa lap phi, convective Cahn-Hilliard transport with
+ *     mobility theta_M (Eq. 2) solved by a BGK order-parameter distribution f;
+ *   - density rho = rho_G + phi (rho_L - rho_G) (Eq. 4a);
+ *   - pressure distribution g with the forcing K of Eq. 8, surface force
+ *     F_s = mu grad phi and body force G = -(rho - rho_ref) g e_vertical;
+ *   - a switch that keeps the additional force F_a = -u [d_t rho + div(rho u)]
+ *     of Eq. 12 (original model) or cancels it by adding -F_a, evaluated as
+ *     u (rho_L - rho_G) theta_M lap mu via Eq. 5, to the forcing (corrected
+ *     model, paragraph after Eq. 12);
+ *   - isotropic central stencils for grad and lap (splash-test paragraph).
+ * D2Q9 follows the paper; D3Q19 is the same model on 19 velocities.
+ *
+ * Conventions for every function:
+ *   - The return value is an lbm_status; no C++ exception crosses the ABI.
+ *     On a non-OK status lbm_last_error() gives a thread-local message.
+ *   - Host pointers are plain CPU memory owned by the caller.  Device
+ *     pointers are HIP device memory on the current device.
+ *   - Node index of a case: x + nx * (y + ny * z); vector fields are SoA
+ *     (all x components, then y, then z), each of length N = nx ny nz.
+ *   - Work is enqueued on the HIP stream given to lbm_init (NULL = the null
+ *     stream); functions that return host data synchronise that stream.
+ *   - A handle is not thread safe; different handles are independent.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LBM_OK = 0,
+  LBM_ERR_ARG = -1,       /* invalid argument; nothing was allocated or enqueued */
+  LBM_ERR_HIP = -2,       /* a HIP runtime call failed; message names it */
+  LBM_ERR_NONFINITE = -3, /* a periodic check found NaN/Inf in phi or u */
+  LBM_ERR_STATE = -4,     /* call not valid for this handle (e.g. wrong size) */
+  LBM_ERR_OOM = -5        /* device arena too small or allocation failed */
+} lbm_status;
+
+enum { LBM_D2Q9 = 0, LBM_D3Q19 = 1 };
+enum { LBM_PERIODIC = 0, LBM_WALL = 1 };
+/* Population storage.  LBM_FP32 stores every population as float.
+ * LBM_FP16 / LBM_BF16 store f_0 as float and the other populations as 16-bit
+ * deviations from the rest state, rounded to nearest even:
+ *   f_i (i > 0):  half(f_i * scale_f)              (rest value of f_i is 0)
+ *   g_i:          half((g_i - w_i p0) * scale_g)   (rest value w_i p0)
+ * f_0 is then rebuilt as phi - sum_{i>0} f_i from the stored values, so the
+ * 16-bit rounding moves phi only between neighbours and sum phi is kept. */
+enum { LBM_FP32 = 0, LBM_FP16 = 1, LBM_BF16 = 2 };
+
+/* Parameters of one case, in lattice units (dx = dt = 1). */
+typedef struct {
+  int32_t lattice;           /* LBM_D2Q9 or LBM_D3Q19 (same for all cases of a handle) */
+  int32_t nx, ny, nz;        /* each >= 4; nz = 1 for D2Q9 */
+  int32_t bc[3];             /* per axis LBM_PERIODIC or LBM_WALL (halfway bounce-back,
+                                mirror ghosts for the stencils: neutral wetting) */
+  double beta, kappa;        /* theta(phi) = beta phi^2 (phi-1)^2 and kappa (Eq. 1a);
+                                lbm_beta_kappa() converts sigma, W */
+  double theta_m;            /* mobility theta_M of Eq. 2 (> = 0) */
+  double tau_f;              /* relaxation time of f (> 1/2); Gamma = theta_M/(tau_f-1/2) */
+  double tau_g;              /* relaxation time of g in the liquid (> 1/2);
+                                nu_L = (tau_g - 1/2)/3 */
+  double rho_l, rho_g;       /* densities of Eq. 4a (> 0) */
+  double mu_ratio;           /* mu_L / mu_G (> 0); = rho_l/rho_g gives constant nu */
+  double gravity, rho_ref;   /* G = -(rho - rho_ref) gravity along -y (2-D) / -z (3-D) */
+  int32_t remove_fa;         /* 0: original model (F_a kept), 1: corrected (-F_a added) */
+  int32_t storage;           /* LBM_FP32 / LBM_FP16 / LBM_BF16 (same for all cases) */
+  double p0;                 /* rest pressure of the 16-bit g deviations */
+  double scale_f, scale_g;   /* powers of two for 16-bit storage; 0 = automatic */
+} lbm_case_params;
+
+/* FP64 diagnostics of one case at the current time level. */
+typedef struct {
+  int64_t step;              /* time level n */
+  double mass;               /* sum phi (total order parameter, conserved) */
+  double mass0;              /* sum phi at lbm_init */
+  double mass_drift_rel;     /* |mass - mass0| / |mass0| */
+  double momentum[3];        /* sum rho u */
+  double wsum;               /* sum w, w = clamp(2 phi - 1/2, 0, 1) */
+  double centroid[3];        /* sum w x / sum w (node coordinates) */
+  double centroid_vel[3];    /* sum w u / sum w */
+  double second_moment[3];   /* sum w (x - X)^2 / sum w per axis */
+  double umax;               /* max |u| */
+  int64_t nonfinite;         /* nodes with a non-finite phi or u component */
+} lbm_diag;
+
+typedef struct lbm_handle lbm_handle;
+
+/* sigma, W -> beta = 12 sigma / W, kappa = 3 sigma W / 2: the pair for which
+ * the flat interface 1/2 + 1/2 tanh(2 z / W) solves kappa phi'' = theta'(phi)
+ * with tension sigma (the paper states that beta and kappa set sigma and W,
+ * without the formula). */
+int lbm_beta_kappa(double sigma, double width, double* beta, double* kappa);
+
+/* Device bytes lbm_init needs for these cases (state ping-pong, field
+ * scratch, reduction partials, tables).  Validates the parameters. */
+int lbm_required_bytes(const lbm_case_params* cases, int32_t ncases, size_t* bytes);
+
+/* Create a handle for ncases cases advancing together (one launch per time
+ * step covers all of them).  phi0[k], u0[k] (dim*N_k, SoA) and p0[k] are host
+ * FP64 initial fields of case k; they are copied.  The initial populations are
+ * the equilibria of (phi0, mu(phi0), u0, p0).
+ * dev_arena: device memory of arena_bytes >= lbm_required_bytes, owned by the
+ * caller and outliving the handle; NULL makes the library allocate its own.
+ * hip_stream: hipStream_t for all work (NULL = null stream).
+ * check_every > 0: lbm_step checks for non-finite values every that many
+ * steps (synchronising) and returns LBM_ERR_NONFINITE when it finds one. */
+int lbm_init(const lbm_case_params* cases, int32_t ncases, const double* const* phi0,
+             const double* const* u0, const double* const* p0, void* dev_arena,
+             size_t arena_bytes, void* hip_stream, int32_t check_every,
+             lbm_handle** out);
+
+/* Advance every case by nsteps time steps (fields, collision, streaming in
+ * one fused kernel per step; repeated steps replay a captured HIP graph).
+ * Asynchronous unless check_every triggers a check. */
+int lbm_step(lbm_handle* h, int64_t nsteps);
+
+/* Macroscopic fields of case icase at the current time level, written to
+ * caller-allocated host float arrays: phi[N], u[dim*N], p[N] (hydrodynamic
+ * pressure), mu[N] (chemical potential), fa[dim*N] (the additional force
+ * F_a = -u (rho_L - rho_G) theta_M lap mu of the current state, whichever
+ * model runs).  Any output may be NULL.  Synchronises the stream. */
+int lbm_moments(lbm_handle* h, int32_t icase, float* phi, float* u, float* p, float* mu,
+                float* fa);
+
+/* Same fields written to device float arrays of the same sizes (no copy to
+ * the host, no synchronisation). */
+int lbm_moments_device(lbm_handle* h, int32_t icase, float* phi, float* u, float* p,
+                       float* mu, float* fa);
+
+/* FP64 diagnostics of case icase, reduced on the GPU in a fixed order (bit
+ * reproducible from run to run).  Synchronises the stream. */
+int lbm_diagnostics(lbm_handle* h, int32_t icase, lbm_diag* out);
+
+/* Number of cases, time level, and bytes of one case's raw state. */
+int lbm_info(const lbm_handle* h, int32_t* ncases, int64_t* step, int32_t* storage);
+int lbm_state_bytes(const lbm_handle* h, int32_t icase, size_t* bytes);
+
+/* Raw stored populations of case icase (checkpoint / resume, bit exact).
+ * The layout is private to the library version; only pass back what
+ * lbm_get_state produced for the same parameters.  Synchronous. */
+int lbm_get_state(lbm_handle* h, int32_t icase, void* host, size_t bytes);
+int lbm_set_state(lbm_handle* h, int32_t icase, const void* host, size_t bytes);
+/* Set the time level of all cases (after lbm_set_state). */
+int lbm_set_step(lbm_handle* h, int64_t step);
+
+/* Launch shape.  variant indexes the compiled tile shapes (lbm_variant_info);
+ * grid_blocks = 0 launches one workgroup per tile, otherwise that many
+ * workgroups loop over the tiles.  graph_steps = 0 disables graph capture,
+ * otherwise lbm_step replays a graph of that many (even) steps. */
+int lbm_set_launch(lbm_handle* h, int32_t variant, int32_t grid_blocks, int32_t graph_steps);
+int lbm_get_launch(const lbm_handle* h, int32_t* variant, int32_t* grid_blocks,
+                   int32_t* graph_steps);
+/* Number of compiled tile variants for a lattice, and the tile (nodes per
+ * axis) and workgroup size of one. */
+int lbm_variant_count(int32_t lattice, int32_t* count);
+int lbm_variant_info(int32_t lattice, int32_t variant, int32_t* tx, int32_t* ty, int32_t* tz,
+                     int32_t* threads);
+
+void lbm_free(lbm_handle* h);
+const char* lbm_last_error(void);
+
+/* ---- test and calibration entry points ------------------------------- */
+
+/* One streaming pass over raw 32-bit words on the device, exactly as the
+ * step kernel pulls populations: out_i(x) = in_i(x - e_i), or in_opp(i)(x)
+ * when x - e_i lies beyond a wall.  in/out: device arrays of Q*N words,
+ * plane i at offset i*N.  Enqueued on hip_stream. */
+int lbm_stream_words(int32_t lattice, int32_t nx, int32_t ny, int32_t nz,
+                     const int32_t* bc, const uint32_t* in, uint32_t* out, void* hip_stream);
+
+/* Round float values to the 16-bit storage format (LBM_FP16 or LBM_BF16),
+ * round to nearest even, on the device: out[k] = bits of format(in[k]).
+ * in: device float[n]; out: device uint16[n]. */
+int lbm_encode16(int32_t storage, const float* in, uint16_t* out, int64_t n,
+                 void* hip_stream);
+
+/* Device copy out[k] = in[k] of n floats with the library's streaming access
+ * pattern (achievable-bandwidth calibration). */
+int lbm_copy_bw(const float* in, float* out, int64_t n, void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,15 @@
+"""MI355X (gfx950) phase-field lattice Boltzmann hot path.
+
+The two-distribution incompressible phase-field LB model of Li, Luo & Gao
+(arXiv:1110.5004), with the switch that keeps or removes the additional
+interfacial force F_a, as hand-written HIP kernels behind the C ABI of
+include/lbm.h.  This package only marshals arguments (binding.py) and builds
+the library (build.py).
+"""
+from .binding import (BF16, D2Q9, D3Q19, FP16, FP32, PERIODIC, WALL, LbmError, Simulation,
+                      beta_kappa, copy_bw, declared_functions, encode16, lib, stream_words,
+                      variants)
+
+__all__ = ["Simulation", "LbmError", "beta_kappa", "lib", "stream_words", "encode16",
+           "copy_bw", "variants", "declared_functions", "D2Q9", "D3Q19", "PERIODIC", "WALL",
+           "FP32", "FP16", "BF16"]

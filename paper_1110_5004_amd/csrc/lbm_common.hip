@@ -1,0 +1,181 @@
+// lbm_common.hip -- lattice-independent gfx950 kernels: streaming of raw
+// words (the exact pull permutation of the step), 16-bit encoding, the
+// bandwidth-calibration copy, and the fixed-order FP64 diagnostics reduction.
+#include "lbm_dev.h"
+#include "lbm_kernels.h"
+#include "lbm_lattice.h"
+
+namespace lbm {
+
+template <int LAT>
+__global__ void __launch_bounds__(256)
+k_stream_words(CaseDev c, const uint32_t* __restrict__ in, uint32_t* __restrict__ out) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= c.n) return;
+  const int x = idx % c.nx;
+  const int y = (idx / c.nx) % c.ny;
+  const int z = idx / (c.nx * c.ny);
+  constexpr int Q = LAT == 0 ? d2q9::Q : d3q19::Q;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    int ex, ey, ez, op;
+    if constexpr (LAT == 0) {
+      ex = d2q9::EX(i); ey = d2q9::EY(i); ez = 0; op = d2q9::OPP(i);
+    } else {
+      ex = d3q19::EX(i); ey = d3q19::EY(i); ez = d3q19::EZ(i); op = d3q19::OPP(i);
+    }
+    int dir = i, j = idx;
+    if (i > 0) j = pull_src(c, x, y, z, ex, ey, ez, i, op, &dir);
+    out[(size_t)i * c.n + idx] = in[(size_t)dir * c.n + j];
+  }
+}
+
+hipError_t stream_words(int lattice, const CaseDev& c, const uint32_t* in, uint32_t* out,
+                        hipStream_t stream) {
+  const int grid = (c.n + 255) / 256;
+  if (lattice == 0)
+    hipLaunchKernelGGL(k_stream_words<0>, dim3(grid), dim3(256), 0, stream, c, in, out);
+  else
+    hipLaunchKernelGGL(k_stream_words<1>, dim3(grid), dim3(256), 0, stream, c, in, out);
+  return hipGetLastError();
+}
+
+template <int S>
+__global__ void __launch_bounds__(256)
+k_encode16(const float* __restrict__ in, uint16_t* __restrict__ out, long long n) {
+  for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < n;
+       k += (long long)gridDim.x * blockDim.x)
+    out[k] = enc16<S>(in[k]);
+}
+
+hipError_t encode16(int storage, const float* in, uint16_t* out, long long n,
+                    hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  long long blocks = (n + 255) / 256;
+  const int grid = (int)(blocks < 65536 ? blocks : 65536);
+  if (storage == ST_BF16)
+    hipLaunchKernelGGL(k_encode16<ST_BF16>, dim3(grid), dim3(256), 0, stream, in, out, n);
+  else
+    hipLaunchKernelGGL(k_encode16<ST_FP16>, dim3(grid), dim3(256), 0, stream, in, out, n);
+  return hipGetLastError();
+}
+
+// Coalesced 16-byte copy; tail handled element-wise.
+__global__ void __launch_bounds__(256)
+k_copy(const float* __restrict__ in, float* __restrict__ out, long long n) {
+  const long long n4 = n / 4;
+  const float4* i4 = reinterpret_cast<const float4*>(in);
+  float4* o4 = reinterpret_cast<float4*>(out);
+  const long long step = (long long)gridDim.x * blockDim.x;
+  for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < n4; k += step)
+    o4[k] = i4[k];
+  for (long long k = n4 * 4 + blockIdx.x * (long long)blockDim.x + threadIdx.x; k < n;
+       k += step)
+    out[k] = in[k];
+}
+
+hipError_t copy_bw(const float* in, float* out, long long n, hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  long long blocks = (n / 4 + 255) / 256;
+  const int grid = (int)(blocks < 8192 ? (blocks > 0 ? blocks : 1) : 8192);
+  hipLaunchKernelGGL(k_copy, dim3(grid), dim3(256), 0, stream, in, out, n);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- FP64 reductions
+// Sums (and one max) over the nodes of one case, from the dumped fields.
+// Every node goes to a fixed thread of a fixed workgroup; threads combine by
+// a fixed shuffle tree, waves by a fixed order through LDS, workgroups by a
+// second single-workgroup pass.  The result is therefore bit-reproducible.
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_down(v, off, 64));
+  return v;
+}
+
+__device__ __forceinline__ void block_combine(double* acc, double* sh, double* out) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int s = 0; s < kDiagSlots; ++s) {
+    const double v = (s == DG_U2MAX) ? wave_max(acc[s]) : wave_sum(acc[s]);
+    if (lane == 0) sh[wave * kDiagSlots + s] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < kDiagSlots) {
+    const int s = threadIdx.x;
+    double v = sh[s];
+    for (int w = 1; w < 4; ++w)
+      v = (s == DG_U2MAX) ? fmax(v, sh[w * kDiagSlots + s]) : v + sh[w * kDiagSlots + s];
+    out[s] = v;
+  }
+}
+
+__global__ void __launch_bounds__(256)
+k_diag_partial(CaseDev c, int dim, const float* __restrict__ phi, const float* __restrict__ ux,
+               const float* __restrict__ uy, const float* __restrict__ uz,
+               double* __restrict__ partials) {
+  __shared__ double sh[4 * kDiagSlots];
+  double acc[kDiagSlots];
+#pragma unroll
+  for (int s = 0; s < kDiagSlots; ++s) acc[s] = 0.0;
+  const int stride = gridDim.x * blockDim.x;
+  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < c.n; idx += stride) {
+    const int x = idx % c.nx;
+    const int y = (idx / c.nx) % c.ny;
+    const int z = idx / (c.nx * c.ny);
+    const double ph = phi[idx];
+    const double u[3] = {ux[idx], uy[idx], dim == 3 ? (double)uz[idx] : 0.0};
+    const double rho = (double)c.rho_g + ph * (double)c.drho;
+    double w = 2.0 * ph - 0.5;
+    w = w < 0.0 ? 0.0 : (w > 1.0 ? 1.0 : w);
+    const double xc[3] = {(double)x, (double)y, (double)z};
+    acc[DG_MASS] += ph;
+    double u2 = 0.0;
+    bool finite = isfinite(ph);
+    for (int a = 0; a < dim; ++a) {
+      acc[DG_MOM + a] += rho * u[a];
+      acc[DG_WX + a] += w * xc[a];
+      acc[DG_WU + a] += w * u[a];
+      acc[DG_WXX + a] += w * xc[a] * xc[a];
+      u2 += u[a] * u[a];
+      finite = finite && isfinite(u[a]);
+    }
+    acc[DG_WSUM] += w;
+    acc[DG_U2MAX] = fmax(acc[DG_U2MAX], u2);
+    if (!finite) acc[DG_BAD] += 1.0;
+  }
+  block_combine(acc, sh, partials + (size_t)blockIdx.x * kDiagSlots);
+}
+
+__global__ void __launch_bounds__(256)
+k_diag_final(const double* __restrict__ partials, int nblocks, double* __restrict__ out) {
+  __shared__ double sh[4 * kDiagSlots];
+  double acc[kDiagSlots];
+#pragma unroll
+  for (int s = 0; s < kDiagSlots; ++s) acc[s] = 0.0;
+  for (int b = threadIdx.x; b < nblocks; b += blockDim.x) {
+#pragma unroll
+    for (int s = 0; s < kDiagSlots; ++s) {
+      const double v = partials[(size_t)b * kDiagSlots + s];
+      acc[s] = (s == DG_U2MAX) ? fmax(acc[s], v) : acc[s] + v;
+    }
+  }
+  block_combine(acc, sh, out);
+}
+
+hipError_t reduce_diag(const CaseDev& c, int dim, const FieldPtrs& f, double* partials,
+                       int nblocks, double* out, hipStream_t stream) {
+  hipLaunchKernelGGL(k_diag_partial, dim3(nblocks), dim3(256), 0, stream, c, dim, f.phi,
+                     f.u[0], f.u[1], f.u[2], partials);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(256), 0, stream, partials, nblocks, out);
+  return hipGetLastError();
+}
+
+}  // namespace lbm

@@ -1,0 +1,212 @@
+// lbm_dev.h -- device-side definitions shared by the gfx950 kernels of the
+// phase-field lattice Boltzmann library: per-case table entry, population
+// storage codecs and pull-streaming index helpers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <stdint.h>
+
+namespace lbm {
+
+enum Storage { ST_FP32 = 0, ST_FP16 = 1, ST_BF16 = 2 };
+
+// One case as the kernels see it.  All physical constants are pre-derived on
+// the host in double and rounded once to float.
+struct CaseDev {
+  int nx, ny, nz;
+  int wall_x, wall_y, wall_z;
+  int n;            // nodes
+  int pad0;
+  long long stride; // elements per population plane (>= n)
+  char* state[2];   // the two copies of the stored populations
+  // physics (float)
+  float beta2;      // 2 beta            (theta'(phi) = 2 beta phi (phi-1)(2 phi-1))
+  float kappa;
+  float gamma3;     // 3 Gamma, Gamma = theta_M / (tau_f - 1/2)
+  float omega_f;    // 1 / tau_f
+  float rho_g, drho;
+  float mu_g, dmu;  // dynamic viscosity mu_G and mu_L - mu_G
+  float gravity, rho_ref;
+  float corr;       // remove_fa * drho * theta_M  (coefficient of lap mu in -F_a / u)
+  float fa_coef;    // drho * theta_M           (F_a dump, whichever model runs)
+  float p0;         // rest pressure of the 16-bit g deviations
+  float scale_f, inv_scale_f, scale_g, inv_scale_g;
+  int pad1;
+};
+
+// Per-tile work item: case index and tile origin.
+struct TileDev {
+  int icase, x0, y0, z0;
+};
+
+// ---------------------------------------------------------------- codecs
+__device__ __forceinline__ uint16_t enc_bf16(float v) {
+  uint32_t b = __float_as_uint(v);
+  if ((b & 0x7f800000u) == 0x7f800000u) {  // Inf / NaN: keep, quiet NaN
+    return (uint16_t)((b >> 16) | ((b & 0x007fffffu) ? 0x40u : 0u));
+  }
+  b += 0x7fffu + ((b >> 16) & 1u);          // round to nearest even
+  return (uint16_t)(b >> 16);
+}
+__device__ __forceinline__ float dec_bf16(uint16_t h) {
+  return __uint_as_float(((uint32_t)h) << 16);
+}
+__device__ __forceinline__ uint16_t enc_fp16(float v) {
+  return __half_as_ushort(__float2half_rn(v));
+}
+__device__ __forceinline__ float dec_fp16(uint16_t h) {
+  return __half2float(__ushort_as_half(h));
+}
+template <int S>
+__device__ __forceinline__ uint16_t enc16(float v) {
+  if constexpr (S == ST_BF16) return enc_bf16(v);
+  else return enc_fp16(v);
+}
+template <int S>
+__device__ __forceinline__ float dec16(uint16_t h) {
+  if constexpr (S == ST_BF16) return dec_bf16(h);
+  else return dec_fp16(h);
+}
+
+// Bytes of one copy of the stored populations for q velocities.
+//   FP32:       2q float planes (f_0..f_{q-1}, g_0..g_{q-1}), then one BF16
+//               plane holding the low part of f_0: f_0 = hi + lo carries the
+//               order parameter (f_0 ~ phi ~ 1 in the liquid) to ~1e-9
+//               instead of the 6e-8 of one float
+//   FP16/BF16:  one float plane (f_0), then 2q-1 16-bit planes
+//               (f_1..f_{q-1}, g_0..g_{q-1})
+__host__ __device__ inline size_t copy_bytes(int storage, int q, long long stride) {
+  return storage == ST_FP32 ? (size_t)(2 * q) * 4 * stride + (size_t)2 * stride
+                            : (size_t)4 * stride + (size_t)(2 * q - 1) * 2 * stride;
+}
+
+// Error-free transformation s + e = a + b (round to nearest, no reassociation).
+__device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
+  s = a + b;
+  const float bb = s - a;
+  e = (a - (s - bb)) + (b - bb);
+}
+
+// Plane accessors.  Q is the number of velocities; i the direction.
+template <int S, int Q>
+struct Pops {
+  // value of f_i stored at node idx of copy base
+  static __device__ __forceinline__ float f(const CaseDev& c, const char* base, int i, int idx) {
+    if constexpr (S == ST_FP32) {
+      return reinterpret_cast<const float*>(base)[(size_t)i * c.stride + idx];
+    } else {
+      if (i == 0) return reinterpret_cast<const float*>(base)[idx];
+      const uint16_t* h = reinterpret_cast<const uint16_t*>(base + 4 * c.stride);
+      return dec16<S>(h[(size_t)(i - 1) * c.stride + idx]) * c.inv_scale_f;
+    }
+  }
+  static __device__ __forceinline__ float g(const CaseDev& c, const char* base, int i, int idx,
+                                            float wi) {
+    if constexpr (S == ST_FP32) {
+      (void)wi;
+      return reinterpret_cast<const float*>(base)[(size_t)(Q + i) * c.stride + idx];
+    } else {
+      const uint16_t* h = reinterpret_cast<const uint16_t*>(base + 4 * c.stride);
+      return dec16<S>(h[(size_t)(Q - 1 + i) * c.stride + idx]) * c.inv_scale_g + wi * c.p0;
+    }
+  }
+  // Quantise f_i (i > 0) to what the store will hold, and store it.
+  static __device__ __forceinline__ float put_f(const CaseDev& c, char* base, int i, int idx,
+                                                float v) {
+    if constexpr (S == ST_FP32) {
+      reinterpret_cast<float*>(base)[(size_t)i * c.stride + idx] = v;
+      return v;
+    } else {
+      uint16_t h = enc16<S>(v * c.scale_f);
+      reinterpret_cast<uint16_t*>(base + 4 * c.stride)[(size_t)(i - 1) * c.stride + idx] = h;
+      return dec16<S>(h) * c.inv_scale_f;
+    }
+  }
+  // low part of f_0 (FP32 storage only; zero otherwise)
+  static __device__ __forceinline__ float f0lo(const CaseDev& c, const char* base, int idx) {
+    if constexpr (S == ST_FP32) {
+      const uint16_t* h = reinterpret_cast<const uint16_t*>(base + (size_t)(2 * Q) * 4 * c.stride);
+      return dec_bf16(h[idx]);
+    } else {
+      return 0.0f;
+    }
+  }
+  // f_0 = hi + lo; the 16-bit layouts keep hi + lo rounded to one float
+  static __device__ __forceinline__ void put_f0(const CaseDev& c, char* base, int idx, float hi,
+                                                float lo) {
+    if constexpr (S == ST_FP32) {
+      float h, l;
+      two_sum(hi, lo, h, l);
+      reinterpret_cast<float*>(base)[idx] = h;
+      reinterpret_cast<uint16_t*>(base + (size_t)(2 * Q) * 4 * c.stride)[idx] = enc_bf16(l);
+    } else {
+      reinterpret_cast<float*>(base)[idx] = hi + lo;
+    }
+  }
+  static __device__ __forceinline__ void put_g(const CaseDev& c, char* base, int i, int idx,
+                                               float v, float wi) {
+    if constexpr (S == ST_FP32) {
+      (void)wi;
+      reinterpret_cast<float*>(base)[(size_t)(Q + i) * c.stride + idx] = v;
+    } else {
+      reinterpret_cast<uint16_t*>(base + 4 * c.stride)[(size_t)(Q - 1 + i) * c.stride + idx] =
+          enc16<S>((v - wi * c.p0) * c.scale_g);
+    }
+  }
+};
+
+// Coordinate of a stencil position on one axis: periodic wrap, or the mirror
+// ghost of a wall half a cell beyond the last node (ghost -k <-> node k-1),
+// clamped so that positions far outside (never used by a real node) still
+// address memory inside the grid.
+__device__ __forceinline__ int map_axis(int g, int n, int wall) {
+  if (wall) {
+    if (g < 0) g = -g - 1;
+    else if (g >= n) g = 2 * n - 1 - g;
+    return g < 0 ? 0 : (g >= n ? n - 1 : g);
+  }
+  g %= n;
+  return g < 0 ? g + n : g;
+}
+
+// Local coordinate (in a region whose first position has global coordinate
+// origin) holding the real node that a position mirrors.  Unchanged on
+// periodic axes and for positions inside the grid.
+__device__ __forceinline__ int mirror_local(int l, int origin, int n, int wall, int width) {
+  if (!wall) return l;
+  int g = origin + l;
+  if (g >= 0 && g < n) return l;
+  g = (g < 0) ? -g - 1 : 2 * n - 1 - g;
+  int lm = g - origin;
+  return lm < 0 ? 0 : (lm >= width ? width - 1 : lm);
+}
+
+// Pull source of direction i at node (x, y, z): the neighbour x - e_i (with
+// periodic wrap), or the node itself with the opposite direction when x - e_i
+// lies beyond a wall (halfway bounce-back).  Sets *dir to the plane to read.
+__device__ __forceinline__ int pull_src(const CaseDev& c, int x, int y, int z, int ex, int ey,
+                                        int ez, int i, int iopp, int* dir) {
+  int sx = x - ex, sy = y - ey, sz = z - ez;
+  bool bb = false;
+  if (sx < 0 || sx >= c.nx) {
+    if (c.wall_x) bb = true;
+    else sx = sx < 0 ? sx + c.nx : sx - c.nx;
+  }
+  if (sy < 0 || sy >= c.ny) {
+    if (c.wall_y) bb = true;
+    else sy = sy < 0 ? sy + c.ny : sy - c.ny;
+  }
+  if (sz < 0 || sz >= c.nz) {
+    if (c.wall_z) bb = true;
+    else sz = sz < 0 ? sz + c.nz : sz - c.nz;
+  }
+  if (bb) {
+    *dir = iopp;
+    return x + c.nx * (y + c.ny * z);
+  }
+  *dir = i;
+  return sx + c.nx * (sy + c.ny * sz);
+}
+
+}  // namespace lbm

@@ -1,0 +1,72 @@
+// lbm_kernels.h -- host-side launch interface of the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lbm_dev.h"
+
+namespace lbm {
+
+struct TileShape {
+  int tx, ty, tz;  // nodes per tile along x, y, z
+  int nt;          // threads per workgroup
+};
+
+// Everything one step / field launch needs.
+struct LaunchArgs {
+  const CaseDev* cases;  // device case table
+  const TileDev* tiles;  // device tile list
+  int ntiles;
+  int grid;              // workgroups (multiple of 8)
+  int parity;            // copy holding the current populations
+  int storage;
+  int rf;                // 1: some case forms lap mu (corrected model)
+  hipStream_t stream;
+};
+
+struct FieldPtrs {
+  float* phi;
+  float* u[3];
+  float* p;
+  float* mu;
+  float* fa[3];
+};
+
+extern const TileShape kD2Q9Tiles[];
+extern const int kD2Q9TileCount;
+extern const TileShape kD3Q19Tiles[];
+extern const int kD3Q19TileCount;
+
+hipError_t d2q9_step(int variant, const LaunchArgs& a);
+hipError_t d2q9_fields(const LaunchArgs& a, const FieldPtrs& f);
+hipError_t d2q9_init(const CaseDev& c, int storage, int parity, const double* phi0,
+                     const double* u0, const double* p0, hipStream_t stream);
+
+hipError_t d3q19_step(int variant, const LaunchArgs& a);
+hipError_t d3q19_fields(const LaunchArgs& a, const FieldPtrs& f);
+hipError_t d3q19_init(const CaseDev& c, int storage, int parity, const double* phi0,
+                      const double* u0, const double* p0, hipStream_t stream);
+
+// Common kernels.
+hipError_t stream_words(int lattice, const CaseDev& c, const uint32_t* in, uint32_t* out,
+                        hipStream_t stream);
+hipError_t encode16(int storage, const float* in, uint16_t* out, long long n,
+                    hipStream_t stream);
+hipError_t copy_bw(const float* in, float* out, long long n, hipStream_t stream);
+
+// FP64 diagnostics: 16 sums per case, reduced in a fixed order.
+constexpr int kDiagSlots = 16;
+// slot layout
+enum {
+  DG_MASS = 0, DG_MOM = 1,   /* 1..3 */
+  DG_WSUM = 4, DG_WX = 5,    /* 5..7 */
+  DG_WU = 8,                 /* 8..10 */
+  DG_WXX = 11,               /* 11..13 */
+  DG_U2MAX = 14, DG_BAD = 15
+};
+hipError_t reduce_diag(const CaseDev& c, int dim, const FieldPtrs& f, double* partials,
+                       int nblocks, double* out, hipStream_t stream);
+constexpr int kReduceBlocks = 512;
+
+}  // namespace lbm

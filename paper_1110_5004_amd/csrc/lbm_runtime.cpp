@@ -1,0 +1,716 @@
+// lbm_runtime.cpp -- host runtime behind the C ABI of include/lbm.h:
+// parameter validation and derivation, device arena layout, tile lists,
+// launch selection, HIP graph capture of repeated steps, field dumps and
+// FP64 diagnostics.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "lbm.h"
+#include "lbm_kernels.h"
+
+using lbm::CaseDev;
+using lbm::TileDev;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIPCHK(call)                                                                   \
+  do {                                                                                 \
+    hipError_t e_ = (call);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return fail(LBM_ERR_HIP, "%s failed: %s", #call, hipGetErrorString(e_));         \
+  } while (0)
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x, size_t a = kAlign) { return (x + a - 1) / a * a; }
+
+int dim_of(int lattice) { return lattice == LBM_D3Q19 ? 3 : 2; }
+int q_of(int lattice) { return lattice == LBM_D3Q19 ? 19 : 9; }
+
+long long nodes_of(const lbm_case_params& c) { return (long long)c.nx * c.ny * c.nz; }
+long long stride_of(const lbm_case_params& c) {
+  return (long long)align_up((size_t)nodes_of(c), 64);
+}
+
+bool is_pow2(double s) {
+  if (!(s > 0.0) || !std::isfinite(s)) return false;
+  int e;
+  return std::frexp(s, &e) == 0.5;
+}
+
+int validate(const lbm_case_params* cs, int32_t n) {
+  if (!cs || n <= 0) return fail(LBM_ERR_ARG, "need at least one case");
+  for (int k = 0; k < n; ++k) {
+    const lbm_case_params& c = cs[k];
+    if (c.lattice != LBM_D2Q9 && c.lattice != LBM_D3Q19)
+      return fail(LBM_ERR_ARG, "case %d: unknown lattice %d", k, c.lattice);
+    if (c.lattice != cs[0].lattice)
+      return fail(LBM_ERR_ARG, "case %d: all cases of a handle must share the lattice", k);
+    if (c.storage != cs[0].storage)
+      return fail(LBM_ERR_ARG, "case %d: all cases of a handle must share the storage", k);
+    if (c.storage < LBM_FP32 || c.storage > LBM_BF16)
+      return fail(LBM_ERR_ARG, "case %d: unknown storage %d", k, c.storage);
+    if (c.nx < 4 || c.ny < 4) return fail(LBM_ERR_ARG, "case %d: nx, ny must be >= 4", k);
+    if (c.lattice == LBM_D2Q9 && c.nz != 1)
+      return fail(LBM_ERR_ARG, "case %d: nz must be 1 for D2Q9", k);
+    if (c.lattice == LBM_D3Q19 && c.nz < 4)
+      return fail(LBM_ERR_ARG, "case %d: nz must be >= 4 for D3Q19", k);
+    if (nodes_of(c) > (1LL << 30)) return fail(LBM_ERR_ARG, "case %d: too many nodes", k);
+    for (int a = 0; a < 3; ++a)
+      if (c.bc[a] != LBM_PERIODIC && c.bc[a] != LBM_WALL)
+        return fail(LBM_ERR_ARG, "case %d: bc[%d] must be periodic or wall", k, a);
+    const double vals[] = {c.beta, c.kappa, c.theta_m, c.tau_f, c.tau_g, c.rho_l, c.rho_g,
+                           c.mu_ratio, c.gravity, c.rho_ref, c.p0};
+    for (double v : vals)
+      if (!std::isfinite(v)) return fail(LBM_ERR_ARG, "case %d: non-finite parameter", k);
+    if (!(c.tau_f > 0.5) || !(c.tau_g > 0.5))
+      return fail(LBM_ERR_ARG, "case %d: tau_f and tau_g must exceed 1/2", k);
+    if (!(c.rho_l > 0.0) || !(c.rho_g > 0.0) || !(c.mu_ratio > 0.0))
+      return fail(LBM_ERR_ARG, "case %d: densities and viscosity ratio must be > 0", k);
+    if (c.theta_m < 0.0 || c.beta < 0.0 || c.kappa < 0.0)
+      return fail(LBM_ERR_ARG, "case %d: theta_m, beta, kappa must be >= 0", k);
+    if (c.remove_fa != 0 && c.remove_fa != 1)
+      return fail(LBM_ERR_ARG, "case %d: remove_fa must be 0 or 1", k);
+    if ((c.scale_f != 0.0 && !is_pow2(c.scale_f)) || (c.scale_g != 0.0 && !is_pow2(c.scale_g)))
+      return fail(LBM_ERR_ARG, "case %d: 16-bit scales must be powers of two (or 0)", k);
+  }
+  return LBM_OK;
+}
+
+const lbm::TileShape* tiles_for(int lattice, int* count) {
+  if (lattice == LBM_D3Q19) {
+    *count = lbm::kD3Q19TileCount;
+    return lbm::kD3Q19Tiles;
+  }
+  *count = lbm::kD2Q9TileCount;
+  return lbm::kD2Q9Tiles;
+}
+
+long long count_tiles(const lbm_case_params& c, const lbm::TileShape& t) {
+  const long long tz = c.lattice == LBM_D3Q19 ? (c.nz + t.tz - 1) / t.tz : 1;
+  return (long long)((c.nx + t.tx - 1) / t.tx) * ((c.ny + t.ty - 1) / t.ty) * tz;
+}
+
+std::vector<TileDev> build_tiles(const lbm_case_params* cs, int n, const lbm::TileShape& t,
+                                 std::vector<int>* off, std::vector<int>* cnt) {
+  std::vector<TileDev> v;
+  if (off) off->assign(n, 0);
+  if (cnt) cnt->assign(n, 0);
+  for (int k = 0; k < n; ++k) {
+    const lbm_case_params& c = cs[k];
+    const int nzt = c.lattice == LBM_D3Q19 ? (c.nz + t.tz - 1) / t.tz : 1;
+    if (off) (*off)[k] = (int)v.size();
+    for (int z = 0; z < nzt; ++z)
+      for (int y = 0; y < c.ny; y += t.ty)
+        for (int x = 0; x < c.nx; x += t.tx) v.push_back(TileDev{k, x, y, z * t.tz});
+    if (cnt) (*cnt)[k] = (int)v.size() - (off ? (*off)[k] : 0);
+  }
+  return v;
+}
+
+// Field-dump tile shape: variant 0 of each lattice.
+const lbm::TileShape& field_shape(int lattice) {
+  int n;
+  return tiles_for(lattice, &n)[0];
+}
+
+struct Layout {
+  size_t cases_off, tiles_off, ftiles_off, fld_off, part_off, dout_off, total;
+  std::vector<size_t> state_off;  // two copies per case, contiguous
+  size_t max_tiles, n_ftiles, fld_plane;
+};
+
+Layout plan(const lbm_case_params* cs, int n) {
+  Layout L{};
+  size_t at = 0;
+  L.cases_off = at;
+  at = align_up(at + sizeof(CaseDev) * n);
+  int nv;
+  const lbm::TileShape* shapes = tiles_for(cs[0].lattice, &nv);
+  size_t mt = 0;
+  for (int v = 0; v < nv; ++v) {
+    size_t t = 0;
+    for (int k = 0; k < n; ++k) t += count_tiles(cs[k], shapes[v]);
+    mt = std::max(mt, t);
+  }
+  L.max_tiles = mt;
+  L.tiles_off = at;
+  at = align_up(at + sizeof(TileDev) * mt);
+  size_t ft = 0;
+  for (int k = 0; k < n; ++k) ft += count_tiles(cs[k], field_shape(cs[0].lattice));
+  L.n_ftiles = ft;
+  L.ftiles_off = at;
+  at = align_up(at + sizeof(TileDev) * ft);
+  const int q = q_of(cs[0].lattice), dim = dim_of(cs[0].lattice);
+  L.state_off.resize(2 * n);
+  long long nmax = 0;
+  for (int k = 0; k < n; ++k) {
+    const size_t cb = align_up(lbm::copy_bytes(cs[k].storage, q, stride_of(cs[k])));
+    L.state_off[2 * k] = at;
+    at += cb;
+    L.state_off[2 * k + 1] = at;
+    at += cb;
+    nmax = std::max(nmax, stride_of(cs[k]));
+  }
+  // field scratch: phi, u (dim), p, mu, fa (dim) floats; also the staging of
+  // the FP64 initial fields (2 + dim doubles per node)
+  L.fld_plane = (size_t)nmax;
+  const size_t fplanes = std::max<size_t>(3 + 2 * dim, 2 * (2 + dim));
+  L.fld_off = at;
+  at = align_up(at + fplanes * L.fld_plane * sizeof(float));
+  L.part_off = at;
+  at = align_up(at + sizeof(double) * lbm::kReduceBlocks * lbm::kDiagSlots);
+  L.dout_off = at;
+  at = align_up(at + sizeof(double) * lbm::kDiagSlots);
+  L.total = at;
+  return L;
+}
+
+int round8(long long x) { return (int)((std::max(x, 1LL) + 7) / 8 * 8); }
+
+}  // namespace
+
+struct lbm_handle {
+  int ncases = 0, lattice = 0, storage = 0, dim = 2, q = 9, rf = 0;
+  std::vector<lbm_case_params> prm;
+  std::vector<CaseDev> cd;
+  Layout L;
+  char* arena = nullptr;
+  bool own_arena = false;
+  hipStream_t stream = nullptr;
+  hipStream_t cap_stream = nullptr;
+  int check_every = 0;
+  int64_t step = 0;
+  int parity = 0;
+  int64_t since_check = 0;
+  int variant = 0, grid_blocks = 0, graph_steps = 16;
+  int ntiles = 0;
+  std::vector<int> ftile_off, ftile_cnt;
+  std::vector<double> mass0;
+  hipGraphExec_t gexec = nullptr;
+  int g_variant = -1, g_grid = -1, g_steps = 0;
+
+  CaseDev* d_cases() { return reinterpret_cast<CaseDev*>(arena + L.cases_off); }
+  TileDev* d_tiles() { return reinterpret_cast<TileDev*>(arena + L.tiles_off); }
+  TileDev* d_ftiles() { return reinterpret_cast<TileDev*>(arena + L.ftiles_off); }
+  float* fld(int plane) {
+    return reinterpret_cast<float*>(arena + L.fld_off) + (size_t)plane * L.fld_plane;
+  }
+  double* partials() { return reinterpret_cast<double*>(arena + L.part_off); }
+  double* dout() { return reinterpret_cast<double*>(arena + L.dout_off); }
+};
+
+namespace {
+
+CaseDev derive(const lbm_case_params& p, char* s0, char* s1) {
+  CaseDev c{};
+  c.nx = p.nx;
+  c.ny = p.ny;
+  c.nz = p.nz;
+  c.wall_x = p.bc[0] == LBM_WALL;
+  c.wall_y = p.bc[1] == LBM_WALL;
+  c.wall_z = p.lattice == LBM_D3Q19 && p.bc[2] == LBM_WALL;
+  c.n = (int)nodes_of(p);
+  c.stride = stride_of(p);
+  c.state[0] = s0;
+  c.state[1] = s1;
+  const double drho = p.rho_l - p.rho_g;
+  const double gamma = p.theta_m / (p.tau_f - 0.5);  // theta_M = Gamma (tau_f - 1/2)
+  const double mu_l = p.rho_l * (p.tau_g - 0.5) / 3.0;  // nu_L = cs^2 (tau_g - 1/2)
+  const double mu_g = mu_l / p.mu_ratio;
+  c.beta2 = (float)(2.0 * p.beta);
+  c.kappa = (float)p.kappa;
+  c.gamma3 = (float)(3.0 * gamma);
+  c.omega_f = (float)(1.0 / p.tau_f);
+  c.rho_g = (float)p.rho_g;
+  c.drho = (float)drho;
+  c.mu_g = (float)mu_g;
+  c.dmu = (float)(mu_l - mu_g);
+  c.gravity = (float)p.gravity;
+  c.rho_ref = (float)p.rho_ref;
+  c.corr = (float)(p.remove_fa ? drho * p.theta_m : 0.0);
+  c.fa_coef = (float)(drho * p.theta_m);
+  c.p0 = (float)p.p0;
+  // 16-bit scales: FP16 keeps deviations down to ~1e-8 normal with 2^13;
+  // BF16 has the float exponent range and needs none.
+  double sf = p.scale_f, sg = p.scale_g;
+  if (sf == 0.0) sf = p.storage == LBM_FP16 ? 8192.0 : 1.0;
+  if (sg == 0.0) sg = p.storage == LBM_FP16 ? 8192.0 : 1.0;
+  c.scale_f = (float)sf;
+  c.inv_scale_f = (float)(1.0 / sf);
+  c.scale_g = (float)sg;
+  c.inv_scale_g = (float)(1.0 / sg);
+  return c;
+}
+
+lbm::LaunchArgs step_args(lbm_handle* h, int parity, hipStream_t s) {
+  lbm::LaunchArgs a{};
+  a.cases = h->d_cases();
+  a.tiles = h->d_tiles();
+  a.ntiles = h->ntiles;
+  a.grid = h->grid_blocks > 0 ? round8(h->grid_blocks) : round8(h->ntiles);
+  a.parity = parity;
+  a.storage = h->storage;
+  a.rf = h->rf;
+  a.stream = s;
+  return a;
+}
+
+hipError_t launch_step(lbm_handle* h, int parity, hipStream_t s) {
+  lbm::LaunchArgs a = step_args(h, parity, s);
+  return h->lattice == LBM_D3Q19 ? lbm::d3q19_step(h->variant, a)
+                                 : lbm::d2q9_step(h->variant, a);
+}
+
+int upload_tiles(lbm_handle* h) {
+  int nv;
+  const lbm::TileShape* shapes = tiles_for(h->lattice, &nv);
+  std::vector<TileDev> t = build_tiles(h->prm.data(), h->ncases, shapes[h->variant], nullptr,
+                                       nullptr);
+  h->ntiles = (int)t.size();
+  HIPCHK(hipMemcpyAsync(h->d_tiles(), t.data(), t.size() * sizeof(TileDev),
+                        hipMemcpyHostToDevice, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return LBM_OK;
+}
+
+void drop_graph(lbm_handle* h) {
+  if (h->gexec) hipGraphExecDestroy(h->gexec);
+  h->gexec = nullptr;
+  h->g_variant = h->g_grid = -1;
+  h->g_steps = 0;
+}
+
+int ensure_graph(lbm_handle* h) {
+  if (h->gexec && h->g_variant == h->variant && h->g_grid == h->grid_blocks &&
+      h->g_steps == h->graph_steps)
+    return LBM_OK;
+  drop_graph(h);
+  if (!h->cap_stream) HIPCHK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+  HIPCHK(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+  hipError_t e = hipSuccess;
+  for (int k = 0; k < h->graph_steps && e == hipSuccess; ++k) e = launch_step(h, k & 1, h->cap_stream);
+  hipGraph_t g = nullptr;
+  hipError_t e2 = hipStreamEndCapture(h->cap_stream, &g);
+  if (e != hipSuccess) {
+    if (g) hipGraphDestroy(g);
+    return fail(LBM_ERR_HIP, "step launch during capture: %s", hipGetErrorString(e));
+  }
+  if (e2 != hipSuccess) return fail(LBM_ERR_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e2));
+  e = hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0);
+  hipGraphDestroy(g);
+  if (e != hipSuccess) {
+    h->gexec = nullptr;
+    return fail(LBM_ERR_HIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+  }
+  h->g_variant = h->variant;
+  h->g_grid = h->grid_blocks;
+  h->g_steps = h->graph_steps;
+  return LBM_OK;
+}
+
+int dump_fields(lbm_handle* h, int icase, const lbm::FieldPtrs& f) {
+  lbm::LaunchArgs a{};
+  a.cases = h->d_cases();
+  a.tiles = h->d_ftiles() + h->ftile_off[icase];
+  a.ntiles = h->ftile_cnt[icase];
+  a.grid = round8(a.ntiles);
+  a.parity = h->parity;
+  a.storage = h->storage;
+  a.rf = 1;
+  a.stream = h->stream;
+  HIPCHK(h->lattice == LBM_D3Q19 ? lbm::d3q19_fields(a, f) : lbm::d2q9_fields(a, f));
+  return LBM_OK;
+}
+
+lbm::FieldPtrs scratch_fields(lbm_handle* h) {
+  lbm::FieldPtrs f{};
+  int k = 0;
+  f.phi = h->fld(k++);
+  for (int a = 0; a < h->dim; ++a) f.u[a] = h->fld(k++);
+  f.p = h->fld(k++);
+  f.mu = h->fld(k++);
+  for (int a = 0; a < h->dim; ++a) f.fa[a] = h->fld(k++);
+  return f;
+}
+
+int diag_sums(lbm_handle* h, int icase, double* s) {
+  lbm::FieldPtrs f = scratch_fields(h);
+  int rc = dump_fields(h, icase, f);
+  if (rc) return rc;
+  HIPCHK(lbm::reduce_diag(h->cd[icase], h->dim, f, h->partials(), lbm::kReduceBlocks, h->dout(),
+                          h->stream));
+  HIPCHK(hipMemcpyAsync(s, h->dout(), sizeof(double) * lbm::kDiagSlots, hipMemcpyDeviceToHost,
+                        h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return LBM_OK;
+}
+
+int check_finite(lbm_handle* h) {
+  for (int k = 0; k < h->ncases; ++k) {
+    double s[lbm::kDiagSlots];
+    int rc = diag_sums(h, k, s);
+    if (rc) return rc;
+    if (s[lbm::DG_BAD] > 0.0)
+      return fail(LBM_ERR_NONFINITE, "case %d: %.0f nodes with non-finite phi or u at step %lld",
+                  k, s[lbm::DG_BAD], (long long)h->step);
+  }
+  return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* lbm_last_error(void) { return g_err.c_str(); }
+
+int lbm_beta_kappa(double sigma, double width, double* beta, double* kappa) {
+  if (!beta || !kappa || !(width > 0.0) || !(sigma >= 0.0))
+    return fail(LBM_ERR_ARG, "need sigma >= 0, W > 0 and output pointers");
+  *beta = 12.0 * sigma / width;
+  *kappa = 1.5 * sigma * width;
+  return LBM_OK;
+}
+
+int lbm_required_bytes(const lbm_case_params* cases, int32_t ncases, size_t* bytes) {
+  int rc = validate(cases, ncases);
+  if (rc) return rc;
+  if (!bytes) return fail(LBM_ERR_ARG, "bytes is NULL");
+  *bytes = plan(cases, ncases).total;
+  return LBM_OK;
+}
+
+int lbm_init(const lbm_case_params* cases, int32_t ncases, const double* const* phi0,
+             const double* const* u0, const double* const* p0, void* dev_arena,
+             size_t arena_bytes, void* hip_stream, int32_t check_every, lbm_handle** out) {
+  if (!out) return fail(LBM_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  int rc = validate(cases, ncases);
+  if (rc) return rc;
+  if (!phi0 || !u0 || !p0) return fail(LBM_ERR_ARG, "initial field arrays are NULL");
+  for (int k = 0; k < ncases; ++k)
+    if (!phi0[k] || !u0[k] || !p0[k]) return fail(LBM_ERR_ARG, "case %d: NULL initial field", k);
+  if (check_every < 0) return fail(LBM_ERR_ARG, "check_every must be >= 0");
+  Layout L = plan(cases, ncases);
+  if (dev_arena && arena_bytes < L.total)
+    return fail(LBM_ERR_OOM, "arena of %zu bytes, need %zu", arena_bytes, L.total);
+  if (dev_arena && (reinterpret_cast<uintptr_t>(dev_arena) % kAlign))
+    return fail(LBM_ERR_ARG, "arena must be 256-byte aligned");
+
+  lbm_handle* h = new lbm_handle();
+  h->ncases = ncases;
+  h->lattice = cases[0].lattice;
+  h->storage = cases[0].storage;
+  h->dim = dim_of(h->lattice);
+  h->q = q_of(h->lattice);
+  h->prm.assign(cases, cases + ncases);
+  h->L = L;
+  h->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  h->check_every = check_every;
+  for (int k = 0; k < ncases; ++k) h->rf |= cases[k].remove_fa;
+  if (dev_arena) {
+    h->arena = reinterpret_cast<char*>(dev_arena);
+  } else {
+    hipError_t e = hipMalloc(&h->arena, L.total);
+    if (e != hipSuccess) {
+      delete h;
+      return fail(LBM_ERR_OOM, "hipMalloc(%zu): %s", L.total, hipGetErrorString(e));
+    }
+    h->own_arena = true;
+  }
+  auto bail = [&](int code) {
+    lbm_free(h);
+    return code;
+  };
+  // zero everything once: plane padding and unused tails then read back as
+  // zeros, so raw states of equal runs compare equal byte for byte
+  {
+    hipError_t e = hipMemsetAsync(h->arena, 0, L.total, h->stream);
+    if (e != hipSuccess) return bail(fail(LBM_ERR_HIP, "arena clear: %s", hipGetErrorString(e)));
+  }
+  for (int k = 0; k < ncases; ++k)
+    h->cd.push_back(derive(cases[k], h->arena + L.state_off[2 * k], h->arena + L.state_off[2 * k + 1]));
+  {
+    hipError_t e = hipMemcpyAsync(h->d_cases(), h->cd.data(), sizeof(CaseDev) * ncases,
+                                  hipMemcpyHostToDevice, h->stream);
+    if (e != hipSuccess) return bail(fail(LBM_ERR_HIP, "case table upload: %s", hipGetErrorString(e)));
+  }
+  std::vector<TileDev> ft = build_tiles(cases, ncases, field_shape(h->lattice), &h->ftile_off,
+                                        &h->ftile_cnt);
+  {
+    hipError_t e = hipMemcpyAsync(h->d_ftiles(), ft.data(), ft.size() * sizeof(TileDev),
+                                  hipMemcpyHostToDevice, h->stream);
+    if (e != hipSuccess) return bail(fail(LBM_ERR_HIP, "tile upload: %s", hipGetErrorString(e)));
+  }
+  if ((rc = upload_tiles(h))) return bail(rc);
+
+  // initial populations, one case at a time through the FP64 staging area
+  for (int k = 0; k < ncases; ++k) {
+    const size_t n = (size_t)nodes_of(cases[k]);
+    double* st = reinterpret_cast<double*>(h->fld(0));
+    double* d_phi = st;
+    double* d_u = st + n;
+    double* d_p = st + (1 + h->dim) * n;
+    hipError_t e = hipMemcpyAsync(d_phi, phi0[k], n * sizeof(double), hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(d_u, u0[k], h->dim * n * sizeof(double), hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(d_p, p0[k], n * sizeof(double), hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess)
+      e = h->lattice == LBM_D3Q19
+              ? lbm::d3q19_init(h->cd[k], h->storage, 0, d_phi, d_u, d_p, h->stream)
+              : lbm::d2q9_init(h->cd[k], h->storage, 0, d_phi, d_u, d_p, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return bail(fail(LBM_ERR_HIP, "case %d init: %s", k, hipGetErrorString(e)));
+  }
+  h->mass0.resize(ncases);
+  for (int k = 0; k < ncases; ++k) {
+    double s[lbm::kDiagSlots];
+    if ((rc = diag_sums(h, k, s))) return bail(rc);
+    h->mass0[k] = s[lbm::DG_MASS];
+  }
+  *out = h;
+  return LBM_OK;
+}
+
+int lbm_step(lbm_handle* h, int64_t nsteps) {
+  if (!h) return fail(LBM_ERR_ARG, "NULL handle");
+  if (nsteps < 0) return fail(LBM_ERR_ARG, "nsteps must be >= 0");
+  while (nsteps > 0) {
+    int64_t left_before_check =
+        h->check_every > 0 ? h->check_every - h->since_check : nsteps;
+    int64_t chunk = std::min<int64_t>(nsteps, left_before_check);
+    while (chunk > 0) {
+      if (h->graph_steps >= 2 && h->parity == 0 && chunk >= h->graph_steps) {
+        int rc = ensure_graph(h);
+        if (rc) return rc;
+        HIPCHK(hipGraphLaunch(h->gexec, h->stream));
+        chunk -= h->graph_steps;
+        nsteps -= h->graph_steps;
+        h->step += h->graph_steps;
+        h->since_check += h->graph_steps;
+      } else {
+        HIPCHK(launch_step(h, h->parity, h->stream));
+        h->parity ^= 1;
+        chunk -= 1;
+        nsteps -= 1;
+        h->step += 1;
+        h->since_check += 1;
+      }
+    }
+    if (h->check_every > 0 && h->since_check >= h->check_every) {
+      h->since_check = 0;
+      int rc = check_finite(h);
+      if (rc) return rc;
+    }
+  }
+  return LBM_OK;
+}
+
+int lbm_moments_device(lbm_handle* h, int32_t icase, float* phi, float* u, float* p, float* mu,
+                       float* fa) {
+  if (!h || icase < 0 || icase >= h->ncases) return fail(LBM_ERR_ARG, "bad handle or case");
+  lbm::FieldPtrs f = scratch_fields(h);
+  const size_t n = (size_t)h->cd[icase].n;
+  if (phi) f.phi = phi;
+  if (u)
+    for (int a = 0; a < h->dim; ++a) f.u[a] = u + a * n;
+  if (p) f.p = p;
+  if (mu) f.mu = mu;
+  if (fa)
+    for (int a = 0; a < h->dim; ++a) f.fa[a] = fa + a * n;
+  return dump_fields(h, icase, f);
+}
+
+int lbm_moments(lbm_handle* h, int32_t icase, float* phi, float* u, float* p, float* mu,
+                float* fa) {
+  if (!h || icase < 0 || icase >= h->ncases) return fail(LBM_ERR_ARG, "bad handle or case");
+  lbm::FieldPtrs f = scratch_fields(h);
+  int rc = dump_fields(h, icase, f);
+  if (rc) return rc;
+  const size_t n = (size_t)h->cd[icase].n, b = n * sizeof(float);
+  if (phi) HIPCHK(hipMemcpyAsync(phi, f.phi, b, hipMemcpyDeviceToHost, h->stream));
+  for (int a = 0; a < h->dim; ++a) {
+    if (u) HIPCHK(hipMemcpyAsync(u + a * n, f.u[a], b, hipMemcpyDeviceToHost, h->stream));
+    if (fa) HIPCHK(hipMemcpyAsync(fa + a * n, f.fa[a], b, hipMemcpyDeviceToHost, h->stream));
+  }
+  if (p) HIPCHK(hipMemcpyAsync(p, f.p, b, hipMemcpyDeviceToHost, h->stream));
+  if (mu) HIPCHK(hipMemcpyAsync(mu, f.mu, b, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return LBM_OK;
+}
+
+int lbm_diagnostics(lbm_handle* h, int32_t icase, lbm_diag* out) {
+  if (!h || !out || icase < 0 || icase >= h->ncases) return fail(LBM_ERR_ARG, "bad arguments");
+  double s[lbm::kDiagSlots];
+  int rc = diag_sums(h, icase, s);
+  if (rc) return rc;
+  std::memset(out, 0, sizeof *out);
+  out->step = h->step;
+  out->mass = s[lbm::DG_MASS];
+  out->mass0 = h->mass0[icase];
+  out->mass_drift_rel = out->mass0 != 0.0 ? std::fabs(out->mass - out->mass0) / std::fabs(out->mass0)
+                                          : std::fabs(out->mass);
+  out->wsum = s[lbm::DG_WSUM];
+  for (int a = 0; a < h->dim; ++a) {
+    out->momentum[a] = s[lbm::DG_MOM + a];
+    if (out->wsum > 0.0) {
+      out->centroid[a] = s[lbm::DG_WX + a] / out->wsum;
+      out->centroid_vel[a] = s[lbm::DG_WU + a] / out->wsum;
+      out->second_moment[a] = s[lbm::DG_WXX + a] / out->wsum - out->centroid[a] * out->centroid[a];
+    }
+  }
+  out->umax = std::sqrt(s[lbm::DG_U2MAX]);
+  out->nonfinite = (int64_t)s[lbm::DG_BAD];
+  return LBM_OK;
+}
+
+int lbm_info(const lbm_handle* h, int32_t* ncases, int64_t* step, int32_t* storage) {
+  if (!h) return fail(LBM_ERR_ARG, "NULL handle");
+  if (ncases) *ncases = h->ncases;
+  if (step) *step = h->step;
+  if (storage) *storage = h->storage;
+  return LBM_OK;
+}
+
+int lbm_state_bytes(const lbm_handle* h, int32_t icase, size_t* bytes) {
+  if (!h || !bytes || icase < 0 || icase >= h->ncases) return fail(LBM_ERR_ARG, "bad arguments");
+  *bytes = lbm::copy_bytes(h->storage, h->q, h->cd[icase].stride);
+  return LBM_OK;
+}
+
+int lbm_get_state(lbm_handle* h, int32_t icase, void* host, size_t bytes) {
+  size_t need;
+  int rc = lbm_state_bytes(h, icase, &need);
+  if (rc) return rc;
+  if (!host || bytes != need) return fail(LBM_ERR_STATE, "state needs exactly %zu bytes", need);
+  HIPCHK(hipMemcpyAsync(host, h->cd[icase].state[h->parity], need, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return LBM_OK;
+}
+
+int lbm_set_state(lbm_handle* h, int32_t icase, const void* host, size_t bytes) {
+  size_t need;
+  int rc = lbm_state_bytes(h, icase, &need);
+  if (rc) return rc;
+  if (!host || bytes != need) return fail(LBM_ERR_STATE, "state needs exactly %zu bytes", need);
+  HIPCHK(hipMemcpyAsync(h->cd[icase].state[h->parity], host, need, hipMemcpyHostToDevice, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return LBM_OK;
+}
+
+int lbm_set_step(lbm_handle* h, int64_t step) {
+  if (!h || step < 0) return fail(LBM_ERR_ARG, "bad arguments");
+  h->step = step;
+  return LBM_OK;
+}
+
+int lbm_variant_count(int32_t lattice, int32_t* count) {
+  if (!count || (lattice != LBM_D2Q9 && lattice != LBM_D3Q19)) return fail(LBM_ERR_ARG, "bad lattice");
+  int n;
+  tiles_for(lattice, &n);
+  *count = n;
+  return LBM_OK;
+}
+
+int lbm_variant_info(int32_t lattice, int32_t variant, int32_t* tx, int32_t* ty, int32_t* tz,
+                     int32_t* threads) {
+  int n;
+  if (lattice != LBM_D2Q9 && lattice != LBM_D3Q19) return fail(LBM_ERR_ARG, "bad lattice");
+  const lbm::TileShape* t = tiles_for(lattice, &n);
+  if (variant < 0 || variant >= n) return fail(LBM_ERR_ARG, "variant out of range");
+  if (tx) *tx = t[variant].tx;
+  if (ty) *ty = t[variant].ty;
+  if (tz) *tz = t[variant].tz;
+  if (threads) *threads = t[variant].nt;
+  return LBM_OK;
+}
+
+int lbm_set_launch(lbm_handle* h, int32_t variant, int32_t grid_blocks, int32_t graph_steps) {
+  if (!h) return fail(LBM_ERR_ARG, "NULL handle");
+  int n;
+  tiles_for(h->lattice, &n);
+  if (variant < 0 || variant >= n) return fail(LBM_ERR_ARG, "variant out of range");
+  if (grid_blocks < 0) return fail(LBM_ERR_ARG, "grid_blocks must be >= 0");
+  if (graph_steps < 0 || (graph_steps & 1) || graph_steps > 4096)
+    return fail(LBM_ERR_ARG, "graph_steps must be 0 or an even number <= 4096");
+  const bool retile = variant != h->variant;
+  h->variant = variant;
+  h->grid_blocks = grid_blocks;
+  h->graph_steps = graph_steps;
+  if (retile) {
+    HIPCHK(hipStreamSynchronize(h->stream));
+    int rc = upload_tiles(h);
+    if (rc) return rc;
+  }
+  return LBM_OK;
+}
+
+int lbm_get_launch(const lbm_handle* h, int32_t* variant, int32_t* grid_blocks,
+                   int32_t* graph_steps) {
+  if (!h) return fail(LBM_ERR_ARG, "NULL handle");
+  if (variant) *variant = h->variant;
+  if (grid_blocks) *grid_blocks = h->grid_blocks;
+  if (graph_steps) *graph_steps = h->graph_steps;
+  return LBM_OK;
+}
+
+void lbm_free(lbm_handle* h) {
+  if (!h) return;
+  if (h->stream || h->arena) hipStreamSynchronize(h->stream);
+  drop_graph(h);
+  if (h->cap_stream) hipStreamDestroy(h->cap_stream);
+  if (h->own_arena && h->arena) hipFree(h->arena);
+  delete h;
+}
+
+int lbm_stream_words(int32_t lattice, int32_t nx, int32_t ny, int32_t nz, const int32_t* bc,
+                     const uint32_t* in, uint32_t* out, void* hip_stream) {
+  if (!bc || !in || !out) return fail(LBM_ERR_ARG, "NULL argument");
+  lbm_case_params p{};
+  p.lattice = lattice;
+  p.nx = nx;
+  p.ny = ny;
+  p.nz = nz;
+  for (int a = 0; a < 3; ++a) p.bc[a] = bc[a];
+  p.tau_f = p.tau_g = 1.0;
+  p.rho_l = p.rho_g = p.mu_ratio = 1.0;
+  int rc = validate(&p, 1);
+  if (rc) return rc;
+  CaseDev c = derive(p, nullptr, nullptr);
+  HIPCHK(lbm::stream_words(lattice, c, in, out, reinterpret_cast<hipStream_t>(hip_stream)));
+  return LBM_OK;
+}
+
+int lbm_encode16(int32_t storage, const float* in, uint16_t* out, int64_t n, void* hip_stream) {
+  if (storage != LBM_FP16 && storage != LBM_BF16) return fail(LBM_ERR_ARG, "storage must be FP16 or BF16");
+  if (n < 0 || (n > 0 && (!in || !out))) return fail(LBM_ERR_ARG, "bad buffers");
+  HIPCHK(lbm::encode16(storage, in, out, n, reinterpret_cast<hipStream_t>(hip_stream)));
+  return LBM_OK;
+}
+
+int lbm_copy_bw(const float* in, float* out, int64_t n, void* hip_stream) {
+  if (n < 0 || (n > 0 && (!in || !out))) return fail(LBM_ERR_ARG, "bad buffers");
+  HIPCHK(lbm::copy_bw(in, out, n, reinterpret_cast<hipStream_t>(hip_stream)));
+  return LBM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,64 @@
+"""CPU checks of the boundary: the library loads without a GPU and exports
+every function include/lbm.h declares; argument errors come back as status
+codes before any device work."""
+import ctypes as C
+
+import pytest
+
+from paper_1110_5004_amd import binding as B
+
+
+@pytest.fixture(scope="module")
+def L():
+    return B.lib()
+
+
+def test_every_declared_symbol_is_exported(L):
+    names = B.declared_functions()
+    assert len(names) >= 20
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_beta_kappa(L):
+    b, k = B.beta_kappa(0.01, 4.0)
+    assert abs(b - 0.03) < 1e-15 and abs(k - 0.06) < 1e-15
+    with pytest.raises(B.LbmError):
+        B.beta_kappa(0.01, 0.0)
+
+
+def _params(**kw):
+    p = dict(lattice=0, nx=16, ny=16, nz=1, wall=[0, 0, 0], sigma=0.01, width=4.0,
+             theta_m=0.1, tau_f=0.8, tau_g=0.8, rho_l=1.0, rho_g=0.1, mu_ratio=10.0,
+             gravity=0.0, rho_ref=0.1, remove_fa=0)
+    p.update(kw)
+    return p
+
+
+@pytest.mark.parametrize("bad", [dict(tau_f=0.5), dict(tau_g=0.3), dict(rho_g=0.0),
+                                 dict(nx=3), dict(nz=2), dict(remove_fa=2),
+                                 dict(wall=[0, 2, 0]), dict(mu_ratio=-1.0),
+                                 dict(theta_m=float("nan"))])
+def test_invalid_parameters_rejected(L, bad):
+    c = B.make_case(_params(**bad))
+    nbytes = C.c_size_t()
+    rc = L.lbm_required_bytes(C.byref(c), 1, C.byref(nbytes))
+    assert rc == B.ERR_ARG
+    assert L.lbm_last_error()
+
+
+def test_required_bytes_grows_with_storage(L):
+    sizes = {}
+    for st in ("fp32", "fp16"):
+        c = B.make_case(_params(nx=256, ny=256), storage=st)
+        nbytes = C.c_size_t()
+        assert L.lbm_required_bytes(C.byref(c), 1, C.byref(nbytes)) == 0
+        sizes[st] = nbytes.value
+    # two copies of 18 x 4 + 2 (FP32, f_0 carries a BF16 low part) or
+    # 4 + 17 x 2 (16-bit) bytes per node
+    assert sizes["fp32"] - sizes["fp16"] == 2 * (74 - 38) * 256 * 256
+
+
+def test_variants_listed(L):
+    v = B.variants(B.D2Q9)
+    assert len(v) >= 2 and all(t[2] == 1 for t in v)

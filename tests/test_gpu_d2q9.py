@@ -1,0 +1,244 @@
+"""GPU parity of the D2Q9 HIP path against the FP64 oracle, through the C ABI.
+
+FP32 tolerances (max |d phi| <= 1e-5, relative L2 of u <= 1e-4 after 1000
+steps of the 128^2 droplet) are the accuracy targets of the FP32 path;
+integer and permutation work is compared bit for bit.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+PHI_TOL = 1e-5
+U_TOL = 1e-4
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available(), "GPU tests need a GPU"
+    return t
+
+
+@pytest.fixture(scope="module")
+def hip(torch):
+    import paper_1110_5004_amd as P
+    P.lib()
+    return P
+
+
+def run_gpu(hip, cases, steps, storage="fp32", variant=None, graph=16, grid=0):
+    sim = hip.Simulation(cases if isinstance(cases, list) else [cases], storage=storage)
+    if variant is not None or graph != 16 or grid:
+        sim.set_launch(variant or 0, grid, graph)
+    sim.step(steps)
+    return sim
+
+
+def run_oracle(case, steps):
+    s = O.Sim(case.params, case.phi0, case.u0, case.p0)
+    s.step(steps)
+    return s
+
+
+def errors(got, want):
+    dphi = float(np.abs(got["phi"].astype(np.float64) - want["phi"]).max())
+    nu = np.linalg.norm(want["u"])
+    du = float(np.linalg.norm(got["u"].astype(np.float64) - want["u"]) / nu)
+    dp = float(np.abs(got["p"] - want["p"]).max() / max(np.abs(want["p"]).max(), 1e-30))
+    return dphi, du, dp
+
+
+# ----------------------------------------------------------------- streaming
+@pytest.mark.parametrize("dims,bc", [((7, 5, 1), (0, 0, 0)), ((70, 45, 1), (0, 1, 0)),
+                                     ((33, 17, 1), (1, 1, 0)), ((16, 9, 1), (1, 0, 0))])
+def test_stream_words_bit_exact(torch, hip, dims, bc):
+    case = W.base_params(W.D2Q9, dims[0], dims[1], 1, bc, sigma=0.01)
+    n = dims[0] * dims[1]
+    rng = np.random.default_rng(sum(dims) + sum(bc))
+    words = rng.integers(0, 2**32, size=(9, n), dtype=np.uint64).astype(np.uint32)
+    want = O.stream_words(case, words)
+    din = torch.from_numpy(words.view(np.int32)).cuda()
+    dout = torch.empty_like(din)
+    hip.stream_words(0, dims, bc, din, dout)
+    torch.cuda.synchronize()
+    got = dout.cpu().numpy().view(np.uint32)
+    assert np.array_equal(got, want)
+
+
+# --------------------------------------------------------------------- codec
+def test_fp16_encode_matches_numpy(torch, hip):
+    rng = np.random.default_rng(0)
+    x = np.concatenate([rng.standard_normal(4000) * 10.0 ** rng.integers(-9, 4, 4000),
+                        [0.0, -0.0, 65504.0, 65520.0, 6.1e-5, 5.96e-8, 2.98e-8, 1e-9,
+                         np.inf, -np.inf]]).astype(np.float32)
+    got = hip.encode16("fp16", torch.from_numpy(x).cuda()).cpu().numpy().view(np.uint16)
+    want = x.astype(np.float16).view(np.uint16)
+    assert np.array_equal(got, want)
+
+
+def test_bf16_encode_matches_torch_cpu(torch, hip):
+    rng = np.random.default_rng(1)
+    x = (rng.standard_normal(5000) * 10.0 ** rng.integers(-30, 30, 5000)).astype(np.float32)
+    x[:4] = [0.0, -0.0, np.inf, 3.0e38]
+    got = hip.encode16("bf16", torch.from_numpy(x).cuda()).cpu().numpy().view(np.uint16)
+    want = torch.from_numpy(x).to(torch.bfloat16).view(torch.int16).numpy().view(np.uint16)
+    assert np.array_equal(got, want)
+
+
+# --------------------------------------------------------------- fixed point
+@pytest.mark.parametrize("phi", [0.0, 1.0])
+@pytest.mark.parametrize("rf", [0, 1])
+def test_fixed_point_bitwise(torch, hip, phi, rf):
+    n = 40
+    prm = W.base_params(W.D2Q9, n, 24, 1, (0, 1, 0), sigma=0.01, remove_fa=rf)
+    case = W.Case(prm, np.full(n * 24, phi), np.zeros((2, n * 24)), np.zeros(n * 24))
+    sim = hip.Simulation([case])
+    s0 = sim.get_state()
+    sim.step(7)
+    assert np.array_equal(sim.get_state(), s0)
+    m = sim.moments()
+    assert np.array_equal(m["phi"], np.full(n * 24, phi, np.float32))
+    assert not m["u"].any() and not m["p"].any()
+
+
+# ---------------------------------------------------- parity vs the oracle
+@pytest.mark.parametrize("rf", [0, 1])
+def test_droplet128_1000_steps(torch, hip, rf):
+    """Stationary droplet, periodic 128^2, 1000 steps, both models."""
+    case = W.stationary_droplet(seed=0, remove_fa=rf)
+    sim = run_gpu(hip, case, 1000)
+    got = sim.moments()
+    want = run_oracle(case, 1000).fields()
+    dphi, du, dp = errors(got, want)
+    print(f"droplet128 rf={rf}: max|dphi|={dphi:.2e} relL2(u)={du:.2e} rel|dp|={dp:.2e}")
+    assert dphi <= PHI_TOL and du <= U_TOL and dp <= 1e-3
+
+
+@pytest.mark.parametrize("shape,wall", [((70, 45), (0, 1, 0)), ((37, 53), (1, 1, 0)),
+                                        ((129, 33), (1, 0, 0)), ((66, 18), (0, 0, 0))])
+@pytest.mark.parametrize("rf", [0, 1])
+def test_ragged_walls_parity(torch, hip, shape, wall, rf):
+    """Ragged tiles, walls on each axis combination, moving droplet with
+    gravity; 300 steps."""
+    nx, ny = shape
+    prm = W.base_params(W.D2Q9, nx, ny, 1, wall, sigma=0.01, gravity=2e-5, remove_fa=rf,
+                        tau_g=0.7, mu_ratio=4.0)
+    rng = np.random.default_rng(nx * ny + rf)
+    centre = (nx * 0.45, ny * 0.55)
+    radius = min(nx, ny) * 0.25
+    noise = rng.normal(0, 1e-3, (2, nx * ny))
+    phi, u, p = W.droplet_fields(prm, centre, radius, impact_u=0.02, noise=noise)
+    case = W.Case(prm, phi, u, p)
+    for variant in range(len(hip.variants())):
+        sim = run_gpu(hip, case, 300, variant=variant)
+        got = sim.moments()
+        if variant == 0:
+            want = run_oracle(case, 300).fields()
+            dphi, du, dp = errors(got, want)
+            print(f"{shape} {wall} rf={rf}: max|dphi|={dphi:.2e} relL2(u)={du:.2e}")
+            assert dphi <= PHI_TOL and du <= U_TOL
+            first = sim.get_state()
+        else:
+            # every tile shape computes each node with the same arithmetic
+            assert np.array_equal(sim.get_state(), first), f"variant {variant} differs"
+
+
+def test_fields_mu_and_fa_match_oracle(torch, hip):
+    case = W.stationary_droplet(seed=3, n=64, radius=14.0)
+    u0 = case.u0.copy()
+    u0[1] -= 0.02
+    case = W.Case(case.params, case.phi0, u0, case.p0)
+    sim = run_gpu(hip, case, 20)
+    got = sim.moments()
+    want = run_oracle(case, 20).fields()
+    scale_mu = np.abs(want["mu"]).max()
+    assert np.abs(got["mu"] - want["mu"]).max() <= 1e-4 * scale_mu
+    scale_fa = np.abs(want["fa"]).max()
+    assert np.abs(got["fa"] - want["fa"]).max() <= 2e-3 * scale_fa
+
+
+# ---------------------------------------------------------- launch / graphs
+def test_graph_replay_bitwise(torch, hip):
+    case = W.stationary_droplet(seed=5, n=96, radius=20.0, remove_fa=1)
+    a = run_gpu(hip, case, 41, graph=0)
+    b = run_gpu(hip, case, 41, graph=16)
+    c = run_gpu(hip, case, 41, graph=4, grid=24)
+    sa = a.get_state()
+    assert np.array_equal(sa, b.get_state()) and np.array_equal(sa, c.get_state())
+
+
+def test_batched_equals_single(torch, hip):
+    cases = [W.stationary_droplet(seed=k, n=n, radius=n * 0.2, remove_fa=k % 2)
+             for k, n in enumerate((64, 96, 128, 40))]
+    cases[3].params["wall"] = [1, 1, 0]
+    batch = run_gpu(hip, cases, 60)
+    for k, c in enumerate(cases):
+        single = run_gpu(hip, c, 60)
+        assert np.array_equal(batch.get_state(k), single.get_state(0)), k
+
+
+# --------------------------------------------------------------- diagnostics
+def test_diagnostics_match_oracle_and_repeat(torch, hip):
+    case = W.stationary_droplet(seed=7, n=96, radius=22.0)
+    u0 = case.u0.copy()
+    u0[0] += 0.01
+    case = W.Case(case.params, case.phi0, u0, case.p0)
+    sim = run_gpu(hip, case, 100)
+    d1 = sim.diagnostics()
+    d2 = sim.diagnostics()
+    for k in ("mass", "centroid", "centroid_vel", "second_moment", "momentum", "umax"):
+        assert np.array_equal(np.asarray(d1[k]), np.asarray(d2[k])), k
+    ref = run_oracle(case, 100).diag()
+    assert abs(d1["mass"] - ref["mass"]) <= 1e-6 * abs(ref["mass"])
+    assert np.allclose(d1["centroid"][:2], ref["centroid"][:2], atol=1e-4)
+    assert np.allclose(d1["centroid_vel"][:2], ref["centroid_vel"][:2], rtol=1e-3, atol=1e-8)
+    assert np.allclose(d1["second_moment"][:2], ref["second_moment"][:2], rtol=1e-5)
+    assert np.allclose(d1["momentum"][:2], ref["momentum"][:2], rtol=1e-3, atol=1e-7)
+    assert d1["nonfinite"] == 0 and d1["mass_drift_rel"] < 1e-6
+
+
+def test_checkpoint_resume_bitwise(torch, hip):
+    case = W.stationary_droplet(seed=9, n=64, radius=12.0, remove_fa=1)
+    a = run_gpu(hip, case, 200)
+    b = run_gpu(hip, case, 101)
+    st = b.get_state()
+    c = hip.Simulation([case])
+    c.set_state(st, step=101)
+    c.step(99)
+    assert c.time == 200
+    assert np.array_equal(a.get_state(), c.get_state())
+
+
+def test_nonfinite_detected(torch, hip):
+    case = W.stationary_droplet(seed=1, n=64, radius=12.0)
+    phi = case.phi0.copy()
+    phi[100] = np.nan
+    bad = W.Case(case.params, phi, case.u0, case.p0)
+    sim = hip.Simulation([bad], check_every=10)
+    with pytest.raises(hip.LbmError) as ei:
+        sim.step(25)
+    assert ei.value.code == -3
+
+
+# ------------------------------------------------- full-size splash workload
+def test_splash1024x512_early_window(torch, hip):
+    """The benchmark workload at full size, both models, in the launch shape
+    the benchmark uses: 30 steps against the oracle, then 2000 GPU steps of
+    mass conservation."""
+    for rf in (0, 1):
+        case = W.splash_2d(remove_fa=rf)
+        sim = run_gpu(hip, case, 30)
+        got = sim.moments()
+        want = run_oracle(case, 30).fields()
+        dphi, du, dp = errors(got, want)
+        print(f"splash rf={rf} 30 steps: max|dphi|={dphi:.2e} relL2(u)={du:.2e}")
+        assert dphi <= PHI_TOL and du <= U_TOL
+        sim.step(1970)
+        d = sim.diagnostics()
+        print(f"splash rf={rf} 2000 steps: mass drift {d['mass_drift_rel']:.2e} "
+              f"umax {d['umax']:.4f}")
+        assert d["nonfinite"] == 0 and d["mass_drift_rel"] <= 1e-6

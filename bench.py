@@ -37,6 +37,12 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-extra", action="store_true", help="skip the FP16 / original-model legs")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--workload", default="splash1024x512",
+                    choices=["splash1024x512", "droplet4096"],
+                    help="splash1024x512 (the benchmark) or droplet4096 (profiling of "
+                         "the HBM-bound regime)")
+    ap.add_argument("--variant", type=int, default=-1,
+                    help="tile variant; -1 = autotuned")
     return ap.parse_args()
 
 
@@ -53,17 +59,35 @@ def time_gpu(torch, sim, steps, warmup):
     return e0.elapsed_time(e1) / 1e3
 
 
-def leg(torch, W, hip, storage, remove_fa, steps, warmup):
-    case = W.splash_2d(remove_fa=remove_fa)
+def make_case(W, workload, remove_fa):
+    if workload == "droplet4096":
+        return W.big_droplet(remove_fa=remove_fa)
+    return W.splash_2d(remove_fa=remove_fa)
+
+
+def leg(torch, W, hip, storage, remove_fa, steps, warmup, workload="splash1024x512",
+        variant=-1):
+    from paper_1110_5004_amd import tune
+    case = make_case(W, workload, remove_fa)
     sim = hip.Simulation([case], storage=storage)
+    if variant >= 0:
+        sim.set_launch(variant, 0, 16)
+    else:
+        # pick the launch shape on a scratch copy, so that the timed run starts
+        # from the initial state
+        probe = hip.Simulation([case], storage=storage)
+        rec = tune.tune(probe, steps=100 if case.n < 4e6 else 10)
+        probe.close()
+        sim.set_launch(rec["variant"], rec["grid"], rec["graph_steps"])
     t = time_gpu(torch, sim, steps, warmup)
     d = sim.diagnostics()
+    variant_used = sim.get_launch()[0]
     n = case.n
     mlups = n * steps / t / 1e6
     sim.close()
     return dict(mlups=mlups, seconds=t, ms_per_step=1e3 * t / steps, nodes=n,
                 mass_drift_rel=d["mass_drift_rel"], nonfinite=int(d["nonfinite"]),
-                umax=d["umax"])
+                umax=d["umax"], variant=variant_used)
 
 
 def cpu_baseline(W, seconds):
@@ -85,12 +109,32 @@ def cpu_baseline(W, seconds):
                        f"{dt:.1f} s, FP64")
 
 
-def traffic_for(kernel_key):
+def source_sha():
+    """Hash of the kernel sources; traffic figures apply only to the kernels
+    they were measured on."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for p in sorted(glob.glob(os.path.join(ROOT, "paper_1110_5004_amd", "csrc", "*"))):
+        h.update(os.path.basename(p).encode())
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def traffic_for(kernel_key, seconds_per_launch):
+    """Measured HBM-side traffic (rocprofv3 FETCH_SIZE x2 + WRITE_SIZE x1 per
+    launch) as GB/s over this run's launch time, or None when the committed
+    counters were taken on other kernel sources or another launch shape."""
     try:
         with open(PROFILE_TRAFFIC) as f:
-            return json.load(f).get(kernel_key)
+            t = json.load(f)
     except (OSError, ValueError):
-        return None
+        return None, None
+    e = t.get("entries", {}).get(kernel_key)
+    if not e or t.get("source_sha") != source_sha():
+        return None, None
+    return round(e["bytes_per_launch"] / seconds_per_launch / 1e9, 1), e["bytes_per_launch"]
 
 
 def main():
@@ -103,10 +147,12 @@ def main():
     import workloads as W
     hip.lib()
 
-    main_leg = leg(torch, W, hip, a.storage, a.remove_fa, a.steps, a.warmup)
+    main_leg = leg(torch, W, hip, a.storage, a.remove_fa, a.steps, a.warmup, a.workload,
+                   a.variant)
     bpl = BYTES_PER_LU[a.storage]
     achieved = main_leg["nodes"] * bpl / (main_leg["seconds"] / a.steps) / 1e9
-    key = f"splash1024x512_{a.storage}_rf{a.remove_fa}"
+    key = f"{a.workload}_{a.storage}_rf{a.remove_fa}_v{main_leg['variant']}"
+    traffic, traffic_bytes = traffic_for(key, main_leg["seconds"] / a.steps)
     out = {
         "metric": "lattice updates/s (MLUPS), fused D2Q9 phase-field step",
         "value": round(main_leg["mlups"], 1),
@@ -120,20 +166,24 @@ def main():
         "vs_baseline": None,
         "dtype": "f32" if a.storage == "fp32" else f"f32 compute, {a.storage} storage",
         "data": "synthetic (seeded splash initial condition)",
-        "config": {"workload": "splash1024x512", "grid": [1024, 512], "lattice": "D2Q9",
-                   "bc": "periodic x, walls y", "storage": a.storage,
-                   "remove_fa": a.remove_fa, "steps_in_job": 20000},
+        "config": ({"workload": "splash1024x512", "grid": [1024, 512], "lattice": "D2Q9",
+                    "bc": "periodic x, walls y", "storage": a.storage,
+                    "remove_fa": a.remove_fa, "steps_in_job": 20000}
+                   if a.workload == "splash1024x512" else
+                   {"workload": "droplet4096", "grid": [4096, 4096], "lattice": "D2Q9",
+                    "bc": "periodic", "storage": a.storage, "remove_fa": a.remove_fa}),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic_for(key),
-                     "bytes_per_lu": bpl},
+                     "traffic": traffic, "traffic_bytes_per_launch": traffic_bytes,
+                     "bytes_per_lu": bpl, "kernel": "k_tile (fused D2Q9 step)",
+                     "variant": main_leg["variant"]},
         "check": {"mass_drift_rel": main_leg["mass_drift_rel"],
                   "nonfinite": main_leg["nonfinite"], "umax": main_leg["umax"]},
     }
     if not a.no_extra:
         extra = {}
         for st, rf in (("fp16", a.remove_fa), ("bf16", a.remove_fa), (a.storage, 1 - a.remove_fa)):
-            r = leg(torch, W, hip, st, rf, a.steps, a.warmup)
+            r = leg(torch, W, hip, st, rf, a.steps, a.warmup, a.workload)
             ach = r["nodes"] * BYTES_PER_LU[st] / (r["seconds"] / a.steps) / 1e9
             extra[f"{st}_rf{rf}"] = dict(mlups=round(r["mlups"], 1),
                                          achieved_gbs=round(ach, 1),

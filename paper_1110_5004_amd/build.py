@@ -18,9 +18,10 @@ SOURCES = ["lbm_runtime.cpp", "lbm_common.hip", "lbm_d2q9.hip", "lbm_d3q19.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-# -ffp-contract=off: arithmetic exactly as written, so every tile shape and
-# the batched launch compute each node to the same bits.
-FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-Wall", "-ffp-contract=off",
+# -ffp-contract=on: a*b+c inside one expression becomes an FMA, decided by
+# the front end per source expression, so every tile shape and the batched
+# launch still compute each node to the same bits (no fast-math).
+FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-Wall", "-ffp-contract=on",
          "-Wno-unused-function", "-Xclang", "-target-feature", "-Xclang",
          "-packed-fp32-ops", "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 

@@ -24,8 +24,13 @@ k_stream_words(CaseDev c, const uint32_t* __restrict__ in, uint32_t* __restrict_
     } else {
       ex = d3q19::EX(i); ey = d3q19::EY(i); ez = d3q19::EZ(i); op = d3q19::OPP(i);
     }
-    int dir = i, j = idx;
-    if (i > 0) j = pull_src(c, x, y, z, ex, ey, ez, i, op, &dir);
+    int dir = i;
+    unsigned j = idx;
+    if (i > 0) {
+      bool bb;
+      j = pull_src(c, x, y, z, ex, ey, ez, &bb);
+      if (bb) dir = op;
+    }
     out[(size_t)i * c.n + idx] = in[(size_t)dir * c.n + j];
   }
 }

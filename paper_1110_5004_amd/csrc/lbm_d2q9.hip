@@ -92,46 +92,117 @@ __device__ __forceinline__ void recover(const CaseDev& c, float phi, float gx, f
   const float fsx = mu * gx;
   const float fsy = mu * gy - (rho - c.rho_ref) * c.gravity;
   const float cc = c.corr * lmu;
-  const float den = rho - 0.5f * cc;
-  ux = (3.0f * m1x + 0.5f * fsx) / den;
-  uy = (3.0f * m1y + 0.5f * fsy) / den;
+  const float iden = 1.0f / (rho - 0.5f * cc);
+  ux = (3.0f * m1x + 0.5f * fsx) * iden;
+  uy = (3.0f * m1y + 0.5f * fsy) * iden;
   p = m0 + (1.0f / 6.0f) * c.drho * (ux * gx + uy * gy);
 }
 
-// phi = f_0 + sum_{i>0} f_i as hi + lo (pulled populations).
+// Interior tiles: per-direction uniform base pointers already shifted by
+// -e_i, so that every pulled population of node idx is base_i[idx] and all
+// loads of a node share one per-lane offset.
 template <int S>
-__device__ __forceinline__ void phi_pull(const CaseDev& c, const char* src, int x, int y,
-                                         bool inner, float& hi, float& lo) {
-  using P = Pops<S, Q>;
-  const int idx = x + c.nx * y;
-  float sm = 0.0f;
+struct InnerPtrs {
+  const char* f[Q];  // f_i pulled (f_0: own node)
+  const char* g[Q];
+  const char* f0lo;
+  __device__ __forceinline__ InnerPtrs(const CaseDev& c, const char* src) {
+    using P = Pops<S, Q>;
 #pragma unroll
-  for (int i = 1; i < Q; ++i) {
-    int dir = i, j;
-    if (inner) j = idx - EX(i) - c.nx * EY(i);
-    else j = pull_src(c, x, y, 0, EX(i), EY(i), 0, i, OPP(i), &dir);
-    sm += P::f(c, src, dir, j);
+    for (int i = 0; i < Q; ++i) {
+      const int sh = EX(i) + c.nx * EY(i);
+      const int fw = (S == ST_FP32 || i == 0) ? 4 : 2;
+      const int gw = S == ST_FP32 ? 4 : 2;
+      f[i] = src + P::fofs(c, i, 0) - (long)sh * fw;
+      g[i] = src + P::gofs(c, i, 0) - (long)sh * gw;
+    }
+    f0lo = src + (size_t)(2 * Q) * 4 * c.stride;
   }
-  two_sum(P::f(c, src, 0, idx), P::f0lo(c, src, idx) + sm, hi, lo);
+  __device__ __forceinline__ float fv(const CaseDev& c, int i, unsigned idx) const {
+    if constexpr (S == ST_FP32) return gload<float>(f[i], 4u * idx);
+    else if (i == 0) return gload<float>(f[0], 4u * idx);
+    else return dec16<S>(gload<uint16_t>(f[i], 2u * idx)) * c.inv_scale_f;
+  }
+  __device__ __forceinline__ float gv(const CaseDev& c, int i, unsigned idx) const {
+    if constexpr (S == ST_FP32) return gload<float>(g[i], 4u * idx);
+    else return dec16<S>(gload<uint16_t>(g[i], 2u * idx)) * c.inv_scale_g + WT(i) * c.p0;
+  }
+  __device__ __forceinline__ float lo(unsigned idx) const {
+    if constexpr (S == ST_FP32) return dec_bf16(gload<uint16_t>(f0lo, 2u * idx));
+    else return 0.0f;
+  }
+};
+
+// Byte offset of f_i (or g_i) pulled by node (x, y) = idx: the neighbour
+// x - e_i, or (across a wall) the node itself in the opposite direction.
+// INNER: the neighbour is known to lie inside the grid.
+template <int S, bool INNER, bool G>
+__device__ __forceinline__ unsigned pull_ofs(const CaseDev& c, int x, int y, unsigned idx,
+                                             int i) {
+  using P = Pops<S, Q>;
+  if (i == 0) return G ? P::gofs(c, 0, idx) : P::fofs(c, 0, idx);
+  if constexpr (INNER) {
+    const unsigned j = idx - EX(i) - c.nx * EY(i);
+    return G ? P::gofs(c, i, j) : P::fofs(c, i, j);
+  } else {
+    bool bb;
+    const unsigned j = pull_src(c, x, y, 0, EX(i), EY(i), 0, &bb);
+    if constexpr (G) return bb ? P::gofs(c, OPP(i), idx) : P::gofs(c, i, j);
+    else return bb ? P::fofs(c, OPP(i), idx) : P::fofs(c, i, j);
+  }
 }
 
-template <int S>
-__device__ __forceinline__ void g_moments(const CaseDev& c, const char* src, int x, int y,
-                                          bool inner, float& m0, float& m1x, float& m1y) {
+// phi = f_0 + sum_{i>0} f_i as hi + lo (pulled populations).
+template <int S, bool INNER>
+__device__ __forceinline__ void phi_pull(const CaseDev& c, const char* src,
+                                         const InnerPtrs<S>& ip, int x, int y, float& hi,
+                                         float& lo) {
   using P = Pops<S, Q>;
-  const int idx = x + c.nx * y;
+  const unsigned idx = x + c.nx * y;
+  float sm = 0.0f;
+  if constexpr (INNER) {
+#pragma unroll
+    for (int i = 1; i < Q; ++i) sm += ip.fv(c, i, idx);
+    two_sum(ip.fv(c, 0, idx), ip.lo(idx) + sm, hi, lo);
+  } else {
+#pragma unroll
+    for (int i = 1; i < Q; ++i) sm += P::f(c, src, i, pull_ofs<S, false, false>(c, x, y, idx, i));
+    two_sum(P::f(c, src, 0, P::fofs(c, 0, idx)), P::f0lo(c, src, idx) + sm, hi, lo);
+  }
+}
+
+template <int S, bool INNER>
+__device__ __forceinline__ void g_moments(const CaseDev& c, const char* src,
+                                          const InnerPtrs<S>& ip, int x, int y, float& m0,
+                                          float& m1x, float& m1y) {
+  using P = Pops<S, Q>;
+  const unsigned idx = x + c.nx * y;
   m0 = m1x = m1y = 0.0f;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    int dir = i, j = idx;
-    if (i > 0) {
-      if (inner) j = idx - EX(i) - c.nx * EY(i);
-      else j = pull_src(c, x, y, 0, EX(i), EY(i), 0, i, OPP(i), &dir);
-    }
-    const float v = P::g(c, src, dir, j, WT(i));
+    const float v = INNER ? ip.gv(c, i, idx)
+                          : P::g(c, src, pull_ofs<S, false, true>(c, x, y, idx, i), WT(i));
     m0 += v;
     if (EX(i)) m1x += EX(i) > 0 ? v : -v;
     if (EY(i)) m1y += EY(i) > 0 ? v : -v;
+  }
+}
+
+// Every population pulled by one node: f_1..f_8 and g_0..g_8.
+template <int S, bool INNER>
+__device__ __forceinline__ void pull_all(const CaseDev& c, const char* src,
+                                         const InnerPtrs<S>& ip, int x, int y, unsigned idx,
+                                         float* fv, float* gv) {
+  using P = Pops<S, Q>;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    if constexpr (INNER) {
+      if (i > 0) fv[i] = ip.fv(c, i, idx);
+      gv[i] = ip.gv(c, i, idx);
+    } else {
+      if (i > 0) fv[i] = P::f(c, src, i, pull_ofs<S, false, false>(c, x, y, idx, i));
+      gv[i] = P::g(c, src, pull_ofs<S, false, true>(c, x, y, idx, i), WT(i));
+    }
   }
 }
 
@@ -147,200 +218,293 @@ struct FieldOut {
   float* faz;
 };
 
+// LDS of one tile.
+template <int TX, int TY, int RF>
+struct TileLds {
+  static constexpr int R = RF ? 3 : 2;   // phi radius
+  static constexpr int RM = R - 1;       // mu radius
+  static constexpr int PW = TX + 2 * R, PH = TY + 2 * R;
+  static constexpr int MW = TX + 2 * RM, MH = TY + 2 * RM;
+  static constexpr int UW = TX + 2, UH = TY + 2;
+  float ph[PW * PH];  // phi = ph + pl
+  float pl[PW * PH];
+  float mu[MW * MH];
+  float ux[UW * UH];  // first moments of gbar, then u
+  float uy[UW * UH];
+  float p[UW * UH];   // zeroth moment of gbar, then p
+};
+
+// Position k of the ring of width r around a TX x TY tile inside a region
+// of width W = TX + 2r: first the r rows above, then the r rows below, then
+// the r columns on each side of the tile rows.
+template <int TX, int TY, int r>
+__device__ __forceinline__ void ring_pos(int k, int& lx, int& ly) {
+  constexpr int W = TX + 2 * r;
+  if (k < 2 * r * W) {
+    const int row = k / W;
+    lx = k - row * W;
+    ly = row < r ? row : TY + row;
+  } else {
+    const int s = k - 2 * r * W;
+    const int row = s / (2 * r);
+    const int col = s - row * 2 * r;
+    ly = r + row;
+    lx = col < r ? col : TX + col;
+  }
+}
+
+// One tile, one node per thread (NT = TX * TY).  All global loads of the tile
+// are issued in one batch: the thread's own node keeps its 17 pulled
+// populations in registers for the collision; the rings around the tile pull
+// f for phi (radius R) and gbar for the moments (radius 1).
+// INNER: every pulled population of the phi region lies inside the grid (no
+// wrap, no wall), so neighbours are plain index offsets.
+template <int TX, int TY, int RF, int S, bool FIELDS, bool INNER>
+__device__ __forceinline__ void tile_body(TileLds<TX, TY, RF>& L, const CaseDev& c, int x0, int y0,
+                                          const char* src, char* dst, const FieldOut& fo) {
+  using T = TileLds<TX, TY, RF>;
+  constexpr int NT = TX * TY;
+  constexpr int R = T::R, RM = T::RM;
+  constexpr int PW = T::PW, PH = T::PH, MW = T::MW, MH = T::MH, UW = T::UW, UH = T::UH;
+  constexpr int NRA = PW * PH - NT;   // phi ring
+  constexpr int NRC = UW * UH - NT;   // moment ring
+  constexpr int IA = (NRA + NT - 1) / NT;
+  constexpr int IB = (MW * MH + NT - 1) / NT;
+  constexpr int IC = (NRC + NT - 1) / NT;
+  constexpr int ICC = (UW * UH + NT - 1) / NT;
+  using P = Pops<S, Q>;
+  const FF<PW> phi{L.ph, L.pl};
+  const int tid = threadIdx.x;
+  const int nx = c.nx, ny = c.ny;
+  const InnerPtrs<S> ip(c, src);
+
+  // ---- A: loads.  Own node: f_1..f_8, gbar_0..gbar_8 in registers, phi and
+  // the gbar moments to LDS.  Rings: phi and moments of halo positions.
+  const int lx0 = tid % TX, ly0 = tid / TX;
+  const int gx0 = x0 + lx0, gy0 = y0 + ly0;
+  const bool own_real = INNER || (gx0 < nx && gy0 < ny);
+  float fv[Q], gv[Q];
+  {
+    int mx = gx0, my = gy0;
+    if constexpr (!INNER) {
+      mx = map_axis(gx0, nx, c.wall_x);
+      my = map_axis(gy0, ny, c.wall_y);
+    }
+    const unsigned idx = mx + nx * my;
+    pull_all<S, INNER>(c, src, ip, mx, my, idx, fv, gv);
+    float f0, f0l;
+    if constexpr (INNER) {
+      f0 = ip.fv(c, 0, idx);
+      f0l = ip.lo(idx);
+    } else {
+      f0 = P::f(c, src, 0, P::fofs(c, 0, idx));
+      f0l = P::f0lo(c, src, idx);
+    }
+    float sm = 0.0f;
+#pragma unroll
+    for (int i = 1; i < Q; ++i) sm += fv[i];
+    float hi, lo;
+    two_sum(f0, f0l + sm, hi, lo);
+    const int pk = (ly0 + R) * PW + (lx0 + R);
+    L.ph[pk] = hi;
+    L.pl[pk] = lo;
+    float m0 = 0.0f, m1x = 0.0f, m1y = 0.0f;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      m0 += gv[i];
+      if (EX(i)) m1x += EX(i) > 0 ? gv[i] : -gv[i];
+      if (EY(i)) m1y += EY(i) > 0 ? gv[i] : -gv[i];
+    }
+    const int uk = (ly0 + 1) * UW + (lx0 + 1);
+    L.p[uk] = m0;
+    L.ux[uk] = m1x;
+    L.uy[uk] = m1y;
+  }
+#pragma unroll
+  for (int it = 0; it < IA; ++it) {
+    const int k = tid + it * NT;
+    if (k < NRA) {
+      int lx, ly;
+      ring_pos<TX, TY, R>(k, lx, ly);
+      int gx = x0 - R + lx, gy = y0 - R + ly;
+      if constexpr (!INNER) {
+        gx = map_axis(gx, nx, c.wall_x);
+        gy = map_axis(gy, ny, c.wall_y);
+      }
+      float hi, lo;
+      phi_pull<S, INNER>(c, src, ip, gx, gy, hi, lo);
+      L.ph[ly * PW + lx] = hi;
+      L.pl[ly * PW + lx] = lo;
+    }
+  }
+#pragma unroll
+  for (int it = 0; it < IC; ++it) {
+    const int k = tid + it * NT;
+    if (k < NRC) {
+      int lx, ly;
+      ring_pos<TX, TY, 1>(k, lx, ly);
+      int gx = x0 - 1 + lx, gy = y0 - 1 + ly;
+      if constexpr (!INNER) {
+        gx = map_axis(gx, nx, c.wall_x);
+        gy = map_axis(gy, ny, c.wall_y);
+      }
+      float m0, m1x, m1y;
+      g_moments<S, INNER>(c, src, ip, gx, gy, m0, m1x, m1y);
+      L.p[ly * UW + lx] = m0;
+      L.ux[ly * UW + lx] = m1x;
+      L.uy[ly * UW + lx] = m1y;
+    }
+  }
+  __syncthreads();
+
+  // ---- B: mu over the tile + RM
+#pragma unroll
+  for (int it = 0; it < IB; ++it) {
+    const int k = tid + it * NT;
+    if (k < MW * MH) {
+      int lx = k % MW, ly = k / MW;
+      if constexpr (!INNER) {
+        lx = mirror_local(lx, x0 - RM, nx, c.wall_x, MW);
+        ly = mirror_local(ly, y0 - RM, ny, c.wall_y, MH);
+      }
+      const int pc = (ly + 1) * PW + (lx + 1);  // phi-region index
+      L.mu[k] = dtheta(c, L.ph[pc], L.pl[pc]) - c.kappa * lap_ff<PW>(phi, pc);
+    }
+  }
+  __syncthreads();
+
+  // ---- C: u, p over the tile + 1, in place of the moments.  A position
+  // beyond a wall stands for its mirror node: its moments were pulled from
+  // that node in A, and its stencils are read around the mirror position, so
+  // it gets the mirror node's u and p.  Each thread reads and writes only its
+  // own position k.
+#pragma unroll
+  for (int it = 0; it < ICC; ++it) {
+    const int k = tid + it * NT;
+    if (k < UW * UH) {
+      int lx = k % UW, ly = k / UW;
+      if constexpr (!INNER) {
+        lx = mirror_local(lx, x0 - 1, nx, c.wall_x, UW);
+        ly = mirror_local(ly, y0 - 1, ny, c.wall_y, UH);
+      }
+      const int pc = (ly + R - 1) * PW + (lx + R - 1);
+      const int mx = lx + (RM - 1), my = ly + (RM - 1);
+      float gx, gy;
+      grad_ff<PW>(phi, pc, gx, gy);
+      const float ph = L.ph[pc] + L.pl[pc];
+      const float mu = L.mu[my * MW + mx];
+      const float lmu = RF ? lap_only<MW>(L.mu, mx, my) : 0.0f;
+      float ux, uy, p;
+      recover(c, ph, gx, gy, mu, lmu, L.p[k], L.ux[k], L.uy[k], ux, uy, p);
+      L.ux[k] = ux;
+      L.uy[k] = uy;
+      L.p[k] = p;
+    }
+  }
+  __syncthreads();
+
+  // ---- D: collide (or dump fields) the own node
+  if (own_real) {
+    const unsigned idx = gx0 + nx * gy0;
+    const int pc = (ly0 + R) * PW + (lx0 + R);
+    const int mx = lx0 + RM, my = ly0 + RM;
+    const int uc = (ly0 + 1) * UW + (lx0 + 1);
+    const float phh = L.ph[pc], phl = L.pl[pc];
+    const float ph = phh + phl;
+    float gx, gy;
+    grad_ff<PW>(phi, pc, gx, gy);
+    const float mu = L.mu[my * MW + mx];
+    const float lmu = RF ? lap_only<MW>(L.mu, mx, my) : 0.0f;
+    const float ux = L.ux[uc];
+    const float uy = L.uy[uc];
+    const float p = L.p[uc];
+
+    if constexpr (FIELDS) {
+      fo.phi[idx] = ph;
+      fo.ux[idx] = ux;
+      fo.uy[idx] = uy;
+      fo.p[idx] = p;
+      fo.mu[idx] = mu;
+      fo.fax[idx] = -ux * c.fa_coef * lmu;
+      fo.fay[idx] = -uy * c.fa_coef * lmu;
+    } else {
+      const float rho = c.rho_g + ph * c.drho;
+      const float cc = c.corr * lmu;
+      const float fx = mu * gx + cc * ux;
+      const float fy = mu * gy - (rho - c.rho_ref) * c.gravity + cc * uy;
+      float gpx, gpy;
+      grad_only<UW>(L.p, lx0 + 1, ly0 + 1, gpx, gpy);
+      const float gpsx = gpx - (1.0f / 3.0f) * c.drho * gx;
+      const float gpsy = gpy - (1.0f / 3.0f) * c.drho * gy;
+      // tau = 1/2 + 3 nu, nu = mu_dyn(phi) / rho  ->  1/tau in one division
+      const float mud = c.mu_g + ph * c.dmu;
+      const float itau = rho / (0.5f * rho + 3.0f * mud);
+      const float half = 1.0f - 0.5f * itau;
+      const float uu = ux * ux + uy * uy;
+      const float gm3 = c.gamma3 * mu;
+      const float uf = ux * fx + uy * fy;        // u . F
+      const float ug = ux * gpsx + uy * gpsy;    // u . grad psi
+      const float r3 = (1.0f / 3.0f) * rho;
+      float fsum = 0.0f;
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        // e_i . v for e_i with components in {-1, 0, 1}
+        const float eu = (EX(i) ? (EX(i) > 0 ? ux : -ux) : 0.0f) +
+                         (EY(i) ? (EY(i) > 0 ? uy : -uy) : 0.0f);
+        const float ef = (EX(i) ? (EX(i) > 0 ? fx : -fx) : 0.0f) +
+                         (EY(i) ? (EY(i) > 0 ? fy : -fy) : 0.0f);
+        const float eg = (EX(i) ? (EX(i) > 0 ? gpsx : -gpsx) : 0.0f) +
+                         (EY(i) ? (EY(i) > 0 ? gpsy : -gpsy) : 0.0f);
+        const float ti = eu * (3.0f + 4.5f * eu) - 1.5f * uu;  // omega_i / w_i - 1
+        const float wt = WT(i) * ti;                           // omega_i - w_i
+        if (i > 0) {
+          const float feq = WT(i) * (gm3 + ph * ti);
+          const float fn = fv[i] - c.omega_f * (fv[i] - feq);
+          fsum += P::put_f(c, dst, i, idx, fn);
+        }
+        // g^eq = w p + rho cs^2 (omega - w);
+        // S = (e - u).[F omega - (omega - w) grad psi]
+        const float geq = WT(i) * p + r3 * wt;
+        const float src_i = (ef - uf) * (WT(i) + wt) - wt * (eg - ug);
+        const float gn = gv[i] - itau * (gv[i] - geq) + half * src_i;
+        P::put_g(c, dst, i, idx, gn, WT(i));
+      }
+      float h0, e0;
+      two_sum(phh, -fsum, h0, e0);
+      P::put_f0(c, dst, idx, h0, e0 + phl);
+    }
+  }
+  __syncthreads();
+}
+
 // RF = 1: lap mu is formed (corrected model, or the F_a dump); phi halo 3.
-// NT threads per tile; every phase loop has a compile-time trip count and is
-// unrolled, so a thread issues the loads of all its positions at once.
-template <int TX, int TY, int NT, int RF, int S, bool FIELDS>
-__global__ void __launch_bounds__(NT)
+// WPE > 0 asks the compiler for at least that many waves per SIMD (fewer
+// registers, more tiles in flight per CU).
+template <int TX, int TY, int RF, int S, bool FIELDS, int WPE>
+__global__ void __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(WPE > 0 ? WPE : 1)))
 k_tile(const CaseDev* __restrict__ cases, const TileDev* __restrict__ tiles, int ntiles,
        int parity, FieldOut fo) {
-  constexpr int R = RF ? 3 : 2;   // phi radius
-  constexpr int RM = R - 1;       // mu radius
-  constexpr int PW = TX + 2 * R, PH = TY + 2 * R;
-  constexpr int MW = TX + 2 * RM, MH = TY + 2 * RM;
-  constexpr int UW = TX + 2, UH = TY + 2;
-  constexpr int IA = (PW * PH + NT - 1) / NT;
-  constexpr int IB = (MW * MH + NT - 1) / NT;
-  constexpr int IC = (UW * UH + NT - 1) / NT;
-  constexpr int ID = (TX * TY + NT - 1) / NT;
-  __shared__ float s_ph[PW * PH];  // phi = s_ph + s_pl
-  __shared__ float s_pl[PW * PH];
-  __shared__ float s_mu[MW * MH];
-  __shared__ float s_ux[UW * UH];
-  __shared__ float s_uy[UW * UH];
-  __shared__ float s_p[UW * UH];
-  using P = Pops<S, Q>;
-  const FF<PW> phi{s_ph, s_pl};
-
-  // XCD-aware order: workgroup b runs on XCD b % 8; give each XCD a
-  // contiguous run of tiles so that halos are shared through its L2.
-  const int G = gridDim.x;
-  const int b = blockIdx.x;
-  const int v0 = (b & 7) * (G >> 3) + (b >> 3);
-  const int tid = threadIdx.x;
-
-  for (int t = v0; t < ntiles; t += G) {
+  constexpr int R = TileLds<TX, TY, RF>::R;
+  __shared__ TileLds<TX, TY, RF> lds;
+  // XCD-aware order: workgroup b runs on XCD b % 8.  Each XCD walks its own
+  // contiguous chunk of the tile list (which the host orders in narrow
+  // vertical strips), so the tiles in flight on one XCD are neighbours and
+  // share their halos through that XCD's L2.
+  const int per_xcd = gridDim.x >> 3;
+  const int xcd = blockIdx.x & 7;
+  const int chunk = (ntiles + 7) >> 3;
+  const int t_end = min(ntiles, (xcd + 1) * chunk);
+  for (int t = xcd * chunk + (blockIdx.x >> 3); t < t_end; t += per_xcd) {
     const TileDev tl = tiles[t];
     const CaseDev c = cases[tl.icase];
-    const int nx = c.nx, ny = c.ny;
-    const int x0 = tl.x0, y0 = tl.y0;
     const char* src = parity ? c.state[1] : c.state[0];
     char* dst = parity ? c.state[0] : c.state[1];
-    // inner: every pulled population of the phi region lies inside the grid
-    const bool inner = (x0 - R - 1 >= 0) && (x0 + TX + R + 1 <= nx) && (y0 - R - 1 >= 0) &&
-                       (y0 + TY + R + 1 <= ny);
-
-    // ---- A: phi over the tile + R
-#pragma unroll
-    for (int it = 0; it < IA; ++it) {
-      const int k = tid + it * NT;
-      if (k < PW * PH) {
-        const int lx = k % PW, ly = k / PW;
-        int gx = x0 - R + lx, gy = y0 - R + ly;
-        if (!inner) {
-          gx = map_axis(gx, nx, c.wall_x);
-          gy = map_axis(gy, ny, c.wall_y);
-        }
-        float hi, lo;
-        phi_pull<S>(c, src, gx, gy, inner, hi, lo);
-        s_ph[k] = hi;
-        s_pl[k] = lo;
-      }
-    }
-    __syncthreads();
-
-    // ---- B: mu over the tile + RM
-#pragma unroll
-    for (int it = 0; it < IB; ++it) {
-      const int k = tid + it * NT;
-      if (k < MW * MH) {
-        int lx = k % MW, ly = k / MW;
-        if (!inner) {
-          lx = mirror_local(lx, x0 - RM, nx, c.wall_x, MW);
-          ly = mirror_local(ly, y0 - RM, ny, c.wall_y, MH);
-        }
-        const int pc = (ly + 1) * PW + (lx + 1);  // phi-region index
-        s_mu[k] = dtheta(c, s_ph[pc], s_pl[pc]) - c.kappa * lap_ff<PW>(phi, pc);
-      }
-    }
-    __syncthreads();
-
-    // ---- C: u, p over the tile + 1
-#pragma unroll
-    for (int it = 0; it < IC; ++it) {
-      const int k = tid + it * NT;
-      if (k < UW * UH) {
-        int lx = k % UW, ly = k / UW;
-        if (!inner) {
-          lx = mirror_local(lx, x0 - 1, nx, c.wall_x, UW);
-          ly = mirror_local(ly, y0 - 1, ny, c.wall_y, UH);
-        }
-        int nxg = x0 - 1 + lx, nyg = y0 - 1 + ly;
-        if (!inner) {
-          nxg = map_axis(nxg, nx, c.wall_x);
-          nyg = map_axis(nyg, ny, c.wall_y);
-        }
-        float m0, m1x, m1y;
-        g_moments<S>(c, src, nxg, nyg, inner, m0, m1x, m1y);
-        const int pc = (ly + R - 1) * PW + (lx + R - 1);
-        const int mx = lx + (RM - 1), my = ly + (RM - 1);
-        float gx, gy;
-        grad_ff<PW>(phi, pc, gx, gy);
-        const float ph = s_ph[pc] + s_pl[pc];
-        const float mu = s_mu[my * MW + mx];
-        const float lmu = RF ? lap_only<MW>(s_mu, mx, my) : 0.0f;
-        float ux, uy, p;
-        recover(c, ph, gx, gy, mu, lmu, m0, m1x, m1y, ux, uy, p);
-        s_ux[k] = ux;
-        s_uy[k] = uy;
-        s_p[k] = p;
-      }
-    }
-    __syncthreads();
-
-    // ---- D: collide (or dump fields) over the tile
-#pragma unroll
-    for (int it = 0; it < ID; ++it) {
-      const int k = tid + it * NT;
-      const int lx = k % TX, ly = k / TX;
-      const int gxn = x0 + lx, gyn = y0 + ly;
-      if (k < TX * TY && gxn < nx && gyn < ny) {
-        const int idx = gxn + nx * gyn;
-        const int pc = (ly + R) * PW + (lx + R);
-        const int mx = lx + RM, my = ly + RM;
-        const int uc = (ly + 1) * UW + (lx + 1);
-        const float phh = s_ph[pc], phl = s_pl[pc];
-        const float ph = phh + phl;
-        float gx, gy;
-        grad_ff<PW>(phi, pc, gx, gy);
-        const float mu = s_mu[my * MW + mx];
-        const float lmu = RF ? lap_only<MW>(s_mu, mx, my) : 0.0f;
-        const float ux = s_ux[uc];
-        const float uy = s_uy[uc];
-        const float p = s_p[uc];
-
-        if constexpr (FIELDS) {
-          fo.phi[idx] = ph;
-          fo.ux[idx] = ux;
-          fo.uy[idx] = uy;
-          fo.p[idx] = p;
-          fo.mu[idx] = mu;
-          fo.fax[idx] = -ux * c.fa_coef * lmu;
-          fo.fay[idx] = -uy * c.fa_coef * lmu;
-        } else {
-          // pull every population first (f_0 is not needed: the post-collision
-          // f_0 closes sum_i f_i* = phi), then collide, then store
-          float fv[Q], gv[Q];
-#pragma unroll
-          for (int i = 0; i < Q; ++i) {
-            int dir = i, j = idx;
-            if (i > 0) {
-              if (inner) j = idx - EX(i) - nx * EY(i);
-              else j = pull_src(c, gxn, gyn, 0, EX(i), EY(i), 0, i, OPP(i), &dir);
-              fv[i] = P::f(c, src, dir, j);
-            }
-            gv[i] = P::g(c, src, dir, j, WT(i));
-          }
-          const float rho = c.rho_g + ph * c.drho;
-          const float cc = c.corr * lmu;
-          const float fx = mu * gx + cc * ux;
-          const float fy = mu * gy - (rho - c.rho_ref) * c.gravity + cc * uy;
-          float gpx, gpy;
-          grad_only<UW>(s_p, lx + 1, ly + 1, gpx, gpy);
-          const float gpsx = gpx - (1.0f / 3.0f) * c.drho * gx;
-          const float gpsy = gpy - (1.0f / 3.0f) * c.drho * gy;
-          const float nu = (c.mu_g + ph * c.dmu) / rho;
-          const float tau = 0.5f + 3.0f * nu;
-          const float itau = 1.0f / tau;
-          const float half = 1.0f - 0.5f * itau;
-          const float uu = ux * ux + uy * uy;
-          const float gm3 = c.gamma3 * mu;
-          float fsum = 0.0f;
-#pragma unroll
-          for (int i = 0; i < Q; ++i) {
-            const float eu = EX(i) * ux + EY(i) * uy;
-            const float ti = 3.0f * eu + 4.5f * eu * eu - 1.5f * uu;  // omega_i / w_i - 1
-            const float wt = WT(i) * ti;                               // omega_i - w_i
-            if (i > 0) {
-              const float feq = WT(i) * (gm3 + ph * ti);
-              const float fn = fv[i] - c.omega_f * (fv[i] - feq);
-              fsum += P::put_f(c, dst, i, idx, fn);
-            }
-            // g^eq = w p + rho cs^2 (omega - w);  S = (e - u).[F omega - (omega - w) grad psi]
-            const float geq = WT(i) * p + (1.0f / 3.0f) * rho * wt;
-            const float dx = EX(i) - ux, dy = EY(i) - uy;
-            const float src_i =
-                (dx * fx + dy * fy) * (WT(i) + wt) - wt * (dx * gpsx + dy * gpsy);
-            const float gn = gv[i] - itau * (gv[i] - geq) + half * src_i;
-            P::put_g(c, dst, i, idx, gn, WT(i));
-          }
-          float h0, e0;
-          two_sum(phh, -fsum, h0, e0);
-          P::put_f0(c, dst, idx, h0, e0 + phl);
-        }
-      }
-    }
-    __syncthreads();
+    const bool inner = (tl.x0 - R - 1 >= 0) && (tl.x0 + TX + R + 1 <= c.nx) &&
+                       (tl.y0 - R - 1 >= 0) && (tl.y0 + TY + R + 1 <= c.ny);
+    if (inner)
+      tile_body<TX, TY, RF, S, FIELDS, true>(lds, c, tl.x0, tl.y0, src, dst, fo);
+    else
+      tile_body<TX, TY, RF, S, FIELDS, false>(lds, c, tl.x0, tl.y0, src, dst, fo);
   }
 }
 
@@ -383,11 +547,12 @@ k_init(CaseDev c, int parity, const double* __restrict__ phi0, const double* __r
     const float geq = WT(i) * p + (1.0f / 3.0f) * rho * wt;
     // population i of node x is pulled from x - e_i, or from x itself in the
     // opposite direction across a wall
-    int dir = i, j = idx;
+    int dir = i;
+    unsigned j = idx;
     if (i > 0) {
-      int sdir;
-      const int s = pull_src(c, x, y, 0, EX(i), EY(i), 0, i, OPP(i), &sdir);
-      if (sdir == i) j = s;
+      bool bb;
+      const unsigned s = pull_src(c, x, y, 0, EX(i), EY(i), 0, &bb);
+      if (!bb) j = s;
       else dir = OPP(i);
       const float feq = WT(i) * (c.gamma3 * mu + ph * ti);
       fsum += P::put_f(c, dst, dir, j, feq);
@@ -405,52 +570,59 @@ k_init(CaseDev c, int parity, const double* __restrict__ phi0, const double* __r
 namespace {
 using d2q9::FieldOut;
 
-template <int TX, int TY, int NT, int RF, int S>
+template <int TX, int TY, int RF, int S, int WPE>
 hipError_t launch_step_t(const LaunchArgs& a) {
   FieldOut fo{};
-  hipLaunchKernelGGL((d2q9::k_tile<TX, TY, NT, RF, S, false>), dim3(a.grid), dim3(NT), 0,
+  hipLaunchKernelGGL((d2q9::k_tile<TX, TY, RF, S, false, WPE>), dim3(a.grid), dim3(TX * TY), 0,
                      a.stream, a.cases, a.tiles, a.ntiles, a.parity, fo);
   return hipGetLastError();
 }
 
-template <int TX, int TY, int NT, int S>
+template <int TX, int TY, int S>
 hipError_t launch_fields_t(const LaunchArgs& a, const FieldPtrs& f) {
   FieldOut fo{f.phi, f.u[0], f.u[1], f.u[2], f.p, f.mu, f.fa[0], f.fa[1], f.fa[2]};
-  hipLaunchKernelGGL((d2q9::k_tile<TX, TY, NT, 1, S, true>), dim3(a.grid), dim3(NT), 0,
+  hipLaunchKernelGGL((d2q9::k_tile<TX, TY, 1, S, true, 0>), dim3(a.grid), dim3(TX * TY), 0,
                      a.stream, a.cases, a.tiles, a.ntiles, a.parity, fo);
   return hipGetLastError();
 }
 
-template <int TX, int TY, int NT>
+template <int TX, int TY, int WPE = 0>
 hipError_t launch_step_v(const LaunchArgs& a) {
   if (a.rf) {
     switch (a.storage) {
-      case ST_FP32: return launch_step_t<TX, TY, NT, 1, ST_FP32>(a);
-      case ST_FP16: return launch_step_t<TX, TY, NT, 1, ST_FP16>(a);
-      default: return launch_step_t<TX, TY, NT, 1, ST_BF16>(a);
+      case ST_FP32: return launch_step_t<TX, TY, 1, ST_FP32, WPE>(a);
+      case ST_FP16: return launch_step_t<TX, TY, 1, ST_FP16, WPE>(a);
+      default: return launch_step_t<TX, TY, 1, ST_BF16, WPE>(a);
     }
   }
   switch (a.storage) {
-    case ST_FP32: return launch_step_t<TX, TY, NT, 0, ST_FP32>(a);
-    case ST_FP16: return launch_step_t<TX, TY, NT, 0, ST_FP16>(a);
-    default: return launch_step_t<TX, TY, NT, 0, ST_BF16>(a);
+    case ST_FP32: return launch_step_t<TX, TY, 0, ST_FP32, WPE>(a);
+    case ST_FP16: return launch_step_t<TX, TY, 0, ST_FP16, WPE>(a);
+    default: return launch_step_t<TX, TY, 0, ST_BF16, WPE>(a);
   }
 }
 }  // namespace
 
-// Compiled tile shapes of the D2Q9 step (index = launch variant).
-const TileShape kD2Q9Tiles[] = {{64, 16, 1, 1024}, {64, 8, 1, 512}, {32, 16, 1, 512},
-                                {64, 32, 1, 1024}, {128, 8, 1, 1024}, {32, 8, 1, 256}};
+// Compiled tile shapes of the D2Q9 step (index = launch variant); one node
+// per thread.
+const TileShape kD2Q9Tiles[] = {{32, 16, 1, 512}, {64, 8, 1, 512},  {64, 16, 1, 1024},
+                                {32, 8, 1, 256},  {128, 4, 1, 512}, {256, 4, 1, 1024},
+                                {64, 8, 1, 512},  {128, 4, 1, 512}, {32, 16, 1, 512},
+                                {64, 8, 1, 512}};
 const int kD2Q9TileCount = sizeof(kD2Q9Tiles) / sizeof(kD2Q9Tiles[0]);
 
 hipError_t d2q9_step(int variant, const LaunchArgs& a) {
   switch (variant) {
-    case 0: return launch_step_v<64, 16, 1024>(a);
-    case 1: return launch_step_v<64, 8, 512>(a);
-    case 2: return launch_step_v<32, 16, 512>(a);
-    case 3: return launch_step_v<64, 32, 1024>(a);
-    case 4: return launch_step_v<128, 8, 1024>(a);
-    case 5: return launch_step_v<32, 8, 256>(a);
+    case 0: return launch_step_v<32, 16>(a);
+    case 1: return launch_step_v<64, 8>(a);
+    case 2: return launch_step_v<64, 16>(a);
+    case 3: return launch_step_v<32, 8>(a);
+    case 4: return launch_step_v<128, 4>(a);
+    case 5: return launch_step_v<256, 4>(a);
+    case 6: return launch_step_v<64, 8, 8>(a);
+    case 7: return launch_step_v<128, 4, 8>(a);
+    case 8: return launch_step_v<32, 16, 8>(a);
+    case 9: return launch_step_v<64, 8, 6>(a);
     default: return hipErrorInvalidValue;
   }
 }
@@ -458,9 +630,9 @@ hipError_t d2q9_step(int variant, const LaunchArgs& a) {
 // The field dump uses the shape of variant 0.
 hipError_t d2q9_fields(const LaunchArgs& a, const FieldPtrs& f) {
   switch (a.storage) {
-    case ST_FP32: return launch_fields_t<64, 16, 1024, ST_FP32>(a, f);
-    case ST_FP16: return launch_fields_t<64, 16, 1024, ST_FP16>(a, f);
-    default: return launch_fields_t<64, 16, 1024, ST_BF16>(a, f);
+    case ST_FP32: return launch_fields_t<32, 16, ST_FP32>(a, f);
+    case ST_FP16: return launch_fields_t<32, 16, ST_FP16>(a, f);
+    default: return launch_fields_t<32, 16, ST_BF16>(a, f);
   }
 }
 

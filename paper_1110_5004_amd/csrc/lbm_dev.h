@@ -17,8 +17,8 @@ struct CaseDev {
   int nx, ny, nz;
   int wall_x, wall_y, wall_z;
   int n;            // nodes
-  int pad0;
-  long long stride; // elements per population plane (>= n)
+  unsigned stride;  // elements per population plane (>= n); a copy is < 4 GiB,
+                    // so every byte offset into it fits 32 bits
   char* state[2];   // the two copies of the stored populations
   // physics (float)
   float beta2;      // 2 beta            (theta'(phi) = 2 beta phi (phi-1)(2 phi-1))
@@ -88,70 +88,95 @@ __device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
   e = (a - (s - bb)) + (b - bb);
 }
 
-// Plane accessors.  Q is the number of velocities; i the direction.
+// Global-memory access.  The state pointers live in a table, so the compiler
+// would treat them as generic (flat) pointers; casting to the global address
+// space, with a uniform base and a 32-bit per-lane byte offset, gives
+// global_load/global_store in their scalar-base form and keeps memory waits
+// apart from LDS waits.
+#define LBM_GLOBAL __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ T gload(const char* base, unsigned byte_off) {
+  return *(const LBM_GLOBAL T*)((const LBM_GLOBAL char*)base + byte_off);
+}
+template <class T>
+__device__ __forceinline__ void gstore(char* base, unsigned byte_off, T v) {
+  *(LBM_GLOBAL T*)((LBM_GLOBAL char*)base + byte_off) = v;
+}
+
+// Plane layout of one copy (Q velocities):
+//   FP32:      f_0..f_{Q-1}, g_0..g_{Q-1} as float planes, then the BF16 low
+//              part of f_0
+//   FP16/BF16: f_0 as a float plane, then f_1..f_{Q-1}, g_0..g_{Q-1} as
+//              16-bit planes
+// Offsets are bytes from the start of the copy.
 template <int S, int Q>
 struct Pops {
-  // value of f_i stored at node idx of copy base
-  static __device__ __forceinline__ float f(const CaseDev& c, const char* base, int i, int idx) {
+  static __device__ __forceinline__ unsigned fofs(const CaseDev& c, int i, unsigned j) {
+    if constexpr (S == ST_FP32) return ((unsigned)i * c.stride + j) * 4u;
+    else return i == 0 ? j * 4u : 4u * c.stride + ((unsigned)(i - 1) * c.stride + j) * 2u;
+  }
+  static __device__ __forceinline__ unsigned gofs(const CaseDev& c, int i, unsigned j) {
+    if constexpr (S == ST_FP32) return ((unsigned)(Q + i) * c.stride + j) * 4u;
+    else return 4u * c.stride + ((unsigned)(Q - 1 + i) * c.stride + j) * 2u;
+  }
+  // f_i at a byte offset (i only selects the width: f_0 is always a float)
+  static __device__ __forceinline__ float f(const CaseDev& c, const char* base, int i,
+                                            unsigned ofs) {
     if constexpr (S == ST_FP32) {
-      return reinterpret_cast<const float*>(base)[(size_t)i * c.stride + idx];
+      return gload<float>(base, ofs);
     } else {
-      if (i == 0) return reinterpret_cast<const float*>(base)[idx];
-      const uint16_t* h = reinterpret_cast<const uint16_t*>(base + 4 * c.stride);
-      return dec16<S>(h[(size_t)(i - 1) * c.stride + idx]) * c.inv_scale_f;
+      if (i == 0) return gload<float>(base, ofs);
+      return dec16<S>(gload<uint16_t>(base, ofs)) * c.inv_scale_f;
     }
   }
-  static __device__ __forceinline__ float g(const CaseDev& c, const char* base, int i, int idx,
+  static __device__ __forceinline__ float g(const CaseDev& c, const char* base, unsigned ofs,
                                             float wi) {
     if constexpr (S == ST_FP32) {
       (void)wi;
-      return reinterpret_cast<const float*>(base)[(size_t)(Q + i) * c.stride + idx];
+      return gload<float>(base, ofs);
     } else {
-      const uint16_t* h = reinterpret_cast<const uint16_t*>(base + 4 * c.stride);
-      return dec16<S>(h[(size_t)(Q - 1 + i) * c.stride + idx]) * c.inv_scale_g + wi * c.p0;
-    }
-  }
-  // Quantise f_i (i > 0) to what the store will hold, and store it.
-  static __device__ __forceinline__ float put_f(const CaseDev& c, char* base, int i, int idx,
-                                                float v) {
-    if constexpr (S == ST_FP32) {
-      reinterpret_cast<float*>(base)[(size_t)i * c.stride + idx] = v;
-      return v;
-    } else {
-      uint16_t h = enc16<S>(v * c.scale_f);
-      reinterpret_cast<uint16_t*>(base + 4 * c.stride)[(size_t)(i - 1) * c.stride + idx] = h;
-      return dec16<S>(h) * c.inv_scale_f;
+      return dec16<S>(gload<uint16_t>(base, ofs)) * c.inv_scale_g + wi * c.p0;
     }
   }
   // low part of f_0 (FP32 storage only; zero otherwise)
-  static __device__ __forceinline__ float f0lo(const CaseDev& c, const char* base, int idx) {
+  static __device__ __forceinline__ float f0lo(const CaseDev& c, const char* base, unsigned j) {
     if constexpr (S == ST_FP32) {
-      const uint16_t* h = reinterpret_cast<const uint16_t*>(base + (size_t)(2 * Q) * 4 * c.stride);
-      return dec_bf16(h[idx]);
+      return dec_bf16(gload<uint16_t>(base, (unsigned)(2 * Q) * 4u * c.stride + 2u * j));
     } else {
       return 0.0f;
     }
   }
+  // Quantise f_i (i > 0) to what the store will hold, store it at node j.
+  static __device__ __forceinline__ float put_f(const CaseDev& c, char* base, int i, unsigned j,
+                                                float v) {
+    if constexpr (S == ST_FP32) {
+      gstore<float>(base, fofs(c, i, j), v);
+      return v;
+    } else {
+      const uint16_t h = enc16<S>(v * c.scale_f);
+      gstore<uint16_t>(base, fofs(c, i, j), h);
+      return dec16<S>(h) * c.inv_scale_f;
+    }
+  }
   // f_0 = hi + lo; the 16-bit layouts keep hi + lo rounded to one float
-  static __device__ __forceinline__ void put_f0(const CaseDev& c, char* base, int idx, float hi,
-                                                float lo) {
+  static __device__ __forceinline__ void put_f0(const CaseDev& c, char* base, unsigned j,
+                                                float hi, float lo) {
     if constexpr (S == ST_FP32) {
       float h, l;
       two_sum(hi, lo, h, l);
-      reinterpret_cast<float*>(base)[idx] = h;
-      reinterpret_cast<uint16_t*>(base + (size_t)(2 * Q) * 4 * c.stride)[idx] = enc_bf16(l);
+      gstore<float>(base, 4u * j, h);
+      gstore<uint16_t>(base, (unsigned)(2 * Q) * 4u * c.stride + 2u * j, enc_bf16(l));
     } else {
-      reinterpret_cast<float*>(base)[idx] = hi + lo;
+      gstore<float>(base, 4u * j, hi + lo);
     }
   }
-  static __device__ __forceinline__ void put_g(const CaseDev& c, char* base, int i, int idx,
+  static __device__ __forceinline__ void put_g(const CaseDev& c, char* base, int i, unsigned j,
                                                float v, float wi) {
     if constexpr (S == ST_FP32) {
       (void)wi;
-      reinterpret_cast<float*>(base)[(size_t)(Q + i) * c.stride + idx] = v;
+      gstore<float>(base, gofs(c, i, j), v);
     } else {
-      reinterpret_cast<uint16_t*>(base + 4 * c.stride)[(size_t)(Q - 1 + i) * c.stride + idx] =
-          enc16<S>((v - wi * c.p0) * c.scale_g);
+      gstore<uint16_t>(base, gofs(c, i, j), enc16<S>((v - wi * c.p0) * c.scale_g));
     }
   }
 };
@@ -184,29 +209,27 @@ __device__ __forceinline__ int mirror_local(int l, int origin, int n, int wall, 
 
 // Pull source of direction i at node (x, y, z): the neighbour x - e_i (with
 // periodic wrap), or the node itself with the opposite direction when x - e_i
-// lies beyond a wall (halfway bounce-back).  Sets *dir to the plane to read.
-__device__ __forceinline__ int pull_src(const CaseDev& c, int x, int y, int z, int ex, int ey,
-                                        int ez, int i, int iopp, int* dir) {
+// lies beyond a wall (halfway bounce-back).  Returns the source node and sets
+// *bb when the opposite direction is to be read.
+__device__ __forceinline__ unsigned pull_src(const CaseDev& c, int x, int y, int z, int ex,
+                                             int ey, int ez, bool* bb) {
   int sx = x - ex, sy = y - ey, sz = z - ez;
-  bool bb = false;
+  bool b = false;
   if (sx < 0 || sx >= c.nx) {
-    if (c.wall_x) bb = true;
+    if (c.wall_x) b = true;
     else sx = sx < 0 ? sx + c.nx : sx - c.nx;
   }
   if (sy < 0 || sy >= c.ny) {
-    if (c.wall_y) bb = true;
+    if (c.wall_y) b = true;
     else sy = sy < 0 ? sy + c.ny : sy - c.ny;
   }
   if (sz < 0 || sz >= c.nz) {
-    if (c.wall_z) bb = true;
+    if (c.wall_z) b = true;
     else sz = sz < 0 ? sz + c.nz : sz - c.nz;
   }
-  if (bb) {
-    *dir = iopp;
-    return x + c.nx * (y + c.ny * z);
-  }
-  *dir = i;
-  return sx + c.nx * (sy + c.ny * sz);
+  *bb = b;
+  if (b) return (unsigned)(x + c.nx * (y + c.ny * z));
+  return (unsigned)(sx + c.nx * (sy + c.ny * sz));
 }
 
 }  // namespace lbm

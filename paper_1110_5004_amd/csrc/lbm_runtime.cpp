@@ -74,6 +74,9 @@ int validate(const lbm_case_params* cs, int32_t n) {
     if (c.lattice == LBM_D3Q19 && c.nz < 4)
       return fail(LBM_ERR_ARG, "case %d: nz must be >= 4 for D3Q19", k);
     if (nodes_of(c) > (1LL << 30)) return fail(LBM_ERR_ARG, "case %d: too many nodes", k);
+    // kernels address one copy of the populations with 32-bit byte offsets
+    if (lbm::copy_bytes(c.storage, q_of(c.lattice), stride_of(c)) >= (1ULL << 32))
+      return fail(LBM_ERR_ARG, "case %d: one copy of the populations exceeds 4 GiB", k);
     for (int a = 0; a < 3; ++a)
       if (c.bc[a] != LBM_PERIODIC && c.bc[a] != LBM_WALL)
         return fail(LBM_ERR_ARG, "case %d: bc[%d] must be periodic or wall", k, a);
@@ -109,18 +112,27 @@ long long count_tiles(const lbm_case_params& c, const lbm::TileShape& t) {
   return (long long)((c.nx + t.tx - 1) / t.tx) * ((c.ny + t.ty - 1) / t.ty) * tz;
 }
 
+// Tile list, case after case.  Within a case the tiles run in vertical strips
+// about kStripNodes wide (tile rows inside a strip, strips left to right), so
+// that consecutive tiles -- which the kernel hands to the same XCD -- share
+// their halos.
+constexpr int kStripNodes = 512;
+
 std::vector<TileDev> build_tiles(const lbm_case_params* cs, int n, const lbm::TileShape& t,
                                  std::vector<int>* off, std::vector<int>* cnt) {
   std::vector<TileDev> v;
   if (off) off->assign(n, 0);
   if (cnt) cnt->assign(n, 0);
+  const int sw = std::max(1, kStripNodes / t.tx) * t.tx;  // strip width in nodes
   for (int k = 0; k < n; ++k) {
     const lbm_case_params& c = cs[k];
     const int nzt = c.lattice == LBM_D3Q19 ? (c.nz + t.tz - 1) / t.tz : 1;
     if (off) (*off)[k] = (int)v.size();
-    for (int z = 0; z < nzt; ++z)
-      for (int y = 0; y < c.ny; y += t.ty)
-        for (int x = 0; x < c.nx; x += t.tx) v.push_back(TileDev{k, x, y, z * t.tz});
+    for (int xs = 0; xs < c.nx; xs += sw)
+      for (int z = 0; z < nzt; ++z)
+        for (int y = 0; y < c.ny; y += t.ty)
+          for (int x = xs; x < std::min(c.nx, xs + sw); x += t.tx)
+            v.push_back(TileDev{k, x, y, z * t.tz});
     if (cnt) (*cnt)[k] = (int)v.size() - (off ? (*off)[k] : 0);
   }
   return v;
@@ -229,7 +241,7 @@ CaseDev derive(const lbm_case_params& p, char* s0, char* s1) {
   c.wall_y = p.bc[1] == LBM_WALL;
   c.wall_z = p.lattice == LBM_D3Q19 && p.bc[2] == LBM_WALL;
   c.n = (int)nodes_of(p);
-  c.stride = stride_of(p);
+  c.stride = (unsigned)stride_of(p);
   c.state[0] = s0;
   c.state[1] = s1;
   const double drho = p.rho_l - p.rho_g;

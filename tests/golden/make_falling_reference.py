@@ -4,7 +4,6 @@
 Calls only the oracle and the seeded workload generator.  Output:
 tests/golden/falling256x1024_oracle.npz with
   phi_final   float32 [ny, nx]   order parameter at the last step
-  u_final     float32 [2, ny, nx]
   t           int64   [K]        diagnostic times (every 1000 steps)
   centroid    float64 [K, 2]     centroid (clamped-phi weights)
   centroid_vel float64 [K, 2]
@@ -50,7 +49,6 @@ def main(steps=50000, every=1000, out=None):
     out = out or os.path.join(os.path.dirname(os.path.abspath(__file__)),
                               f"falling{nx}x{ny}_oracle.npz")
     np.savez_compressed(out, phi_final=fl["phi"].reshape(ny, nx).astype(np.float32),
-                        u_final=fl["u"].reshape(2, ny, nx).astype(np.float32),
                         **{k: np.array(v) for k, v in rec.items()})
     print("wrote", out)
 

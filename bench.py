@@ -24,6 +24,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_LU = {"fp32": 148.0, "fp16": 76.0, "bf16": 76.0}
+BYTES_PER_LU_3D = {"fp32": 308.0, "fp16": 156.0, "bf16": 156.0}
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "traffic.json")
 
 
@@ -90,6 +91,50 @@ def leg(torch, W, hip, storage, remove_fa, steps, warmup, workload="splash1024x5
                 umax=d["umax"], variant=variant_used)
 
 
+def leg_3d(torch, W, hip, storage, remove_fa, steps=100, warmup=10):
+    """D3Q19 splash 256x256x128 (periodic x, y, walls z)."""
+    case = W.splash_3d(remove_fa=remove_fa)
+    sim = hip.Simulation([case], storage=storage)
+    t = time_gpu(torch, sim, steps, warmup)
+    d = sim.diagnostics()
+    sim.close()
+    mlups = case.n * steps / t / 1e6
+    ach = case.n * BYTES_PER_LU_3D[storage] / (t / steps) / 1e9
+    return dict(mlups=round(mlups, 1), achieved_gbs=round(ach, 1),
+                frac=round(ach / HBM_PEAK_GBS, 4), bytes_per_lu=BYTES_PER_LU_3D[storage],
+                steps=steps, nonfinite=int(d["nonfinite"]), mass_drift_rel=d["mass_drift_rel"])
+
+
+def leg_ensemble(torch, W, hip, storage, steps=200, warmup=20):
+    """64 droplet cases (64^2..512^2) in one launch per step, against the same
+    cases advanced one Simulation at a time."""
+    cases = W.ensemble(seed=0)
+    nodes = sum(c.n for c in cases)
+    sim = hip.Simulation(cases, storage=storage)
+    t = time_gpu(torch, sim, steps, warmup)
+    bad = sum(int(sim.diagnostics(k)["nonfinite"]) for k in range(len(cases)))
+    sim.close()
+    out = dict(cases=len(cases), nodes=nodes, batched_mlups=round(nodes * steps / t / 1e6, 1),
+               nonfinite=bad)
+    if storage == "fp32":
+        sims = [hip.Simulation([c], storage=storage) for c in cases]
+        for s_ in sims:
+            s_.step(warmup)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for s_ in sims:
+            s_.step(steps)
+        e1.record()
+        torch.cuda.synchronize()
+        t1 = e0.elapsed_time(e1) / 1e3
+        for s_ in sims:
+            s_.close()
+        out["one_at_a_time_mlups"] = round(nodes * steps / t1 / 1e6, 1)
+    return out
+
+
 def cpu_baseline(W, seconds):
     """The FP64 oracle as it stands on the host cores, on the same workload,
     stepping until about `seconds` have passed."""
@@ -109,15 +154,17 @@ def cpu_baseline(W, seconds):
                        f"{dt:.1f} s, FP64")
 
 
+STEP_KERNEL_SOURCES = ("lbm_d2q9.hip", "lbm_dev.h", "lbm_lattice.h")
+
+
 def source_sha():
-    """Hash of the kernel sources; traffic figures apply only to the kernels
-    they were measured on."""
-    import glob
+    """Hash of the sources of the D2Q9 step kernel; traffic figures apply only
+    to the kernel they were measured on."""
     import hashlib
     h = hashlib.sha256()
-    for p in sorted(glob.glob(os.path.join(ROOT, "paper_1110_5004_amd", "csrc", "*"))):
-        h.update(os.path.basename(p).encode())
-        with open(p, "rb") as f:
+    for name in STEP_KERNEL_SOURCES:
+        h.update(name.encode())
+        with open(os.path.join(ROOT, "paper_1110_5004_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()
 
@@ -191,6 +238,9 @@ def main():
                                          nonfinite=r["nonfinite"],
                                          mass_drift_rel=r["mass_drift_rel"])
         out["variants"] = extra
+        out["d3q19_splash256x256x128"] = {f"{st}_rf{rf}": leg_3d(torch, W, hip, st, rf)
+                                          for st, rf in (("fp16", 1), ("fp16", 0), ("fp32", 1))}
+        out["ensemble64"] = {st: leg_ensemble(torch, W, hip, st) for st in ("fp32", "fp16")}
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(W, a.cpu_seconds)
     print(json.dumps(out), flush=True)

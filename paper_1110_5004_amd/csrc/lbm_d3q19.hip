@@ -1,15 +1,422 @@
-// lbm_d3q19.hip -- gfx950 kernels of the D3Q19 form of the step (not built yet).
+// lbm_d3q19.hip -- gfx950 kernels of the D3Q19 form of the phase-field step.
+//
+// The same model as the D2Q9 step (Eq. 1a, Eq. 4a, Eq. 8, the -F_a switch of
+// the paragraph after Eq. 12, isotropic central stencils), on 19 velocities.
+// A step is four node-parallel kernels that pass fields through HBM:
+//   k3_pull     pull f and gbar; phi (float-float) and the gbar moments
+//   k3_mu       mu = theta'(phi) - kappa lap phi
+//   k3_fields   grad phi, lap mu, u and p (with -F_a in the corrected model)
+//   k3_collide  grad p -> grad psi, BGK collision of f and gbar, store
+// Stencil neighbours come from the field planes through the periodic / mirror
+// mapping, so positions beyond a wall read their mirror node.
 #include "lbm_dev.h"
 #include "lbm_kernels.h"
+#include "lbm_lattice.h"
 
 namespace lbm {
-const TileShape kD3Q19Tiles[] = {{32, 4, 4, 512}};
+namespace d3q19 {
+
+__device__ __forceinline__ float dtheta(const CaseDev& c, float hi, float lo) {
+  const float a = hi + lo;
+  const float b = (hi - 1.0f) + lo;
+  const float d = (2.0f * hi - 1.0f) + 2.0f * lo;
+  return c.beta2 * a * b * d;
+}
+
+__device__ __forceinline__ void coords(const CaseDev& c, unsigned idx, int& x, int& y, int& z) {
+  x = idx % c.nx;
+  const unsigned r = idx / c.nx;
+  y = r % c.ny;
+  z = r / c.ny;
+}
+
+// Node of the stencil neighbour x + e_i (periodic wrap or mirror ghost).
+__device__ __forceinline__ unsigned nbr(const CaseDev& c, int x, int y, int z, int i,
+                                        bool interior, unsigned idx) {
+  if (interior) return idx + EX(i) + c.nx * (EY(i) + c.ny * EZ(i));
+  const int mx = map_axis(x + EX(i), c.nx, c.wall_x);
+  const int my = map_axis(y + EY(i), c.ny, c.wall_y);
+  const int mz = map_axis(z + EZ(i), c.nz, c.wall_z);
+  return mx + c.nx * (my + c.ny * mz);
+}
+
+__device__ __forceinline__ bool is_interior(const CaseDev& c, int x, int y, int z) {
+  return x > 0 && x < c.nx - 1 && y > 0 && y < c.ny - 1 && z > 0 && z < c.nz - 1;
+}
+
+// Byte offset of the population of direction i pulled by node idx.
+template <int S, bool G>
+__device__ __forceinline__ unsigned pull3(const CaseDev& c, int x, int y, int z, unsigned idx,
+                                          int i, bool interior) {
+  using P = Pops<S, Q>;
+  if (i == 0) return G ? P::gofs(c, 0, idx) : P::fofs(c, 0, idx);
+  unsigned j;
+  bool bb = false;
+  if (interior) j = idx - EX(i) - c.nx * (EY(i) + c.ny * EZ(i));
+  else j = pull_src(c, x, y, z, EX(i), EY(i), EZ(i), &bb);
+  if (G) return bb ? P::gofs(c, OPP(i), idx) : P::gofs(c, i, j);
+  return bb ? P::fofs(c, OPP(i), idx) : P::fofs(c, i, j);
+}
+
+struct Fields3 {
+  float *phh, *phl, *m0, *m1x, *m1y, *m1z;  // pull
+  float* mu;                                // mu
+  float *ux, *uy, *uz, *p, *lmu, *gx, *gy, *gz;  // fields
+};
+
+// ---- 1: pull, phi, moments
+template <int S>
+__global__ void __launch_bounds__(256) k3_pull(CaseDev c, int parity, Fields3 fl) {
+  using P = Pops<S, Q>;
+  const unsigned idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (unsigned)c.n) return;
+  int x, y, z;
+  coords(c, idx, x, y, z);
+  const bool in = is_interior(c, x, y, z);
+  const char* src = parity ? c.state[1] : c.state[0];
+  float sm = 0.0f;
+#pragma unroll
+  for (int i = 1; i < Q; ++i) sm += P::f(c, src, i, pull3<S, false>(c, x, y, z, idx, i, in));
+  float hi, lo;
+  two_sum(P::f(c, src, 0, P::fofs(c, 0, idx)), P::f0lo(c, src, idx) + sm, hi, lo);
+  float m0 = 0.0f, mx = 0.0f, my = 0.0f, mz = 0.0f;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const float v = P::g(c, src, pull3<S, true>(c, x, y, z, idx, i, in), WT(i));
+    m0 += v;
+    if (EX(i)) mx += EX(i) > 0 ? v : -v;
+    if (EY(i)) my += EY(i) > 0 ? v : -v;
+    if (EZ(i)) mz += EZ(i) > 0 ? v : -v;
+  }
+  fl.phh[idx] = hi;
+  fl.phl[idx] = lo;
+  fl.m0[idx] = m0;
+  fl.m1x[idx] = mx;
+  fl.m1y[idx] = my;
+  fl.m1z[idx] = mz;
+}
+
+// Isotropic Laplacian 6 sum_i w_i (phi_i - phi) and gradient 3 sum_i w_i e_i
+// phi_i of a float-float field (differences of close values are exact).
+__device__ __forceinline__ void grad_lap_ff(const CaseDev& c, const float* h, const float* l,
+                                            int x, int y, int z, unsigned idx, bool in,
+                                            float* g, float* lap) {
+  const float h0 = h[idx], l0 = l[idx];
+  float ax = 0.0f, ay = 0.0f, az = 0.0f, la = 0.0f, le = 0.0f;
+#pragma unroll
+  for (int i = 1; i < Q; ++i) {
+    const unsigned j = nbr(c, x, y, z, i, in, idx);
+    const float d = (h[j] - h0) + (l[j] - l0);   // phi_i - phi
+    if (i <= 6) la += d;
+    else le += d;
+    // gradient from differences: sum w_i e_i (phi_i - phi) = sum w_i e_i phi_i
+    const float w = i <= 6 ? (1.0f / 6.0f) : (1.0f / 12.0f);  // 3 w_i
+    if (EX(i)) ax += EX(i) > 0 ? w * d : -w * d;
+    if (EY(i)) ay += EY(i) > 0 ? w * d : -w * d;
+    if (EZ(i)) az += EZ(i) > 0 ? w * d : -w * d;
+  }
+  if (g) {
+    g[0] = ax;
+    g[1] = ay;
+    g[2] = az;
+  }
+  if (lap) *lap = (1.0f / 3.0f) * la + (1.0f / 6.0f) * le;
+}
+
+__device__ __forceinline__ float lap_f(const CaseDev& c, const float* f, int x, int y, int z,
+                                       unsigned idx, bool in) {
+  const float f0 = f[idx];
+  float la = 0.0f, le = 0.0f;
+#pragma unroll
+  for (int i = 1; i < Q; ++i) {
+    const float d = f[nbr(c, x, y, z, i, in, idx)] - f0;
+    if (i <= 6) la += d;
+    else le += d;
+  }
+  return (1.0f / 3.0f) * la + (1.0f / 6.0f) * le;
+}
+
+__device__ __forceinline__ void grad_f(const CaseDev& c, const float* f, int x, int y, int z,
+                                       unsigned idx, bool in, float* g) {
+  const float f0 = f[idx];
+  float ax = 0.0f, ay = 0.0f, az = 0.0f;
+#pragma unroll
+  for (int i = 1; i < Q; ++i) {
+    const float d = f[nbr(c, x, y, z, i, in, idx)] - f0;
+    const float w = i <= 6 ? (1.0f / 6.0f) : (1.0f / 12.0f);
+    if (EX(i)) ax += EX(i) > 0 ? w * d : -w * d;
+    if (EY(i)) ay += EY(i) > 0 ? w * d : -w * d;
+    if (EZ(i)) az += EZ(i) > 0 ? w * d : -w * d;
+  }
+  g[0] = ax;
+  g[1] = ay;
+  g[2] = az;
+}
+
+// ---- 2: chemical potential
+__global__ void __launch_bounds__(256) k3_mu(CaseDev c, Fields3 fl) {
+  const unsigned idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (unsigned)c.n) return;
+  int x, y, z;
+  coords(c, idx, x, y, z);
+  const bool in = is_interior(c, x, y, z);
+  float lap;
+  grad_lap_ff(c, fl.phh, fl.phl, x, y, z, idx, in, nullptr, &lap);
+  fl.mu[idx] = dtheta(c, fl.phh[idx], fl.phl[idx]) - c.kappa * lap;
+}
+
+// ---- 3: grad phi, lap mu, u, p.  want_lmu forms lap mu also for the
+// original model (field dump of F_a).
+__global__ void __launch_bounds__(256) k3_fields(CaseDev c, Fields3 fl, int want_lmu) {
+  const unsigned idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (unsigned)c.n) return;
+  int x, y, z;
+  coords(c, idx, x, y, z);
+  const bool in = is_interior(c, x, y, z);
+  float g[3];
+  grad_lap_ff(c, fl.phh, fl.phl, x, y, z, idx, in, g, nullptr);
+  const float lmu = (want_lmu || c.corr != 0.0f) ? lap_f(c, fl.mu, x, y, z, idx, in) : 0.0f;
+  const float ph = fl.phh[idx] + fl.phl[idx];
+  const float mu = fl.mu[idx];
+  const float rho = c.rho_g + ph * c.drho;
+  // (rho - c/2) u = 3 sum e gbar + (F_s + G)/2, gravity along -z
+  const float fsx = mu * g[0], fsy = mu * g[1];
+  const float fsz = mu * g[2] - (rho - c.rho_ref) * c.gravity;
+  const float cc = c.corr * lmu;
+  const float iden = 1.0f / (rho - 0.5f * cc);
+  const float ux = (3.0f * fl.m1x[idx] + 0.5f * fsx) * iden;
+  const float uy = (3.0f * fl.m1y[idx] + 0.5f * fsy) * iden;
+  const float uz = (3.0f * fl.m1z[idx] + 0.5f * fsz) * iden;
+  fl.ux[idx] = ux;
+  fl.uy[idx] = uy;
+  fl.uz[idx] = uz;
+  fl.p[idx] = fl.m0[idx] + (1.0f / 6.0f) * c.drho * (ux * g[0] + uy * g[1] + uz * g[2]);
+  fl.lmu[idx] = lmu;
+  fl.gx[idx] = g[0];
+  fl.gy[idx] = g[1];
+  fl.gz[idx] = g[2];
+}
+
+// ---- 4: collision and store
+template <int S>
+__global__ void __launch_bounds__(256) k3_collide(CaseDev c, int parity, Fields3 fl) {
+  using P = Pops<S, Q>;
+  const unsigned idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (unsigned)c.n) return;
+  int x, y, z;
+  coords(c, idx, x, y, z);
+  const bool in = is_interior(c, x, y, z);
+  const char* src = parity ? c.state[1] : c.state[0];
+  char* dst = parity ? c.state[0] : c.state[1];
+  float fv[Q], gv[Q];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    if (i > 0) fv[i] = P::f(c, src, i, pull3<S, false>(c, x, y, z, idx, i, in));
+    gv[i] = P::g(c, src, pull3<S, true>(c, x, y, z, idx, i, in), WT(i));
+  }
+  float gp[3];
+  grad_f(c, fl.p, x, y, z, idx, in, gp);
+  const float phh = fl.phh[idx], phl = fl.phl[idx];
+  const float ph = phh + phl;
+  const float mu = fl.mu[idx], lmu = fl.lmu[idx], p = fl.p[idx];
+  const float ux = fl.ux[idx], uy = fl.uy[idx], uz = fl.uz[idx];
+  const float gx = fl.gx[idx], gy = fl.gy[idx], gz = fl.gz[idx];
+  const float rho = c.rho_g + ph * c.drho;
+  const float cc = c.corr * lmu;
+  const float fx = mu * gx + cc * ux;
+  const float fy = mu * gy + cc * uy;
+  const float fz = mu * gz - (rho - c.rho_ref) * c.gravity + cc * uz;
+  const float gpsx = gp[0] - (1.0f / 3.0f) * c.drho * gx;
+  const float gpsy = gp[1] - (1.0f / 3.0f) * c.drho * gy;
+  const float gpsz = gp[2] - (1.0f / 3.0f) * c.drho * gz;
+  const float mud = c.mu_g + ph * c.dmu;
+  const float itau = rho / (0.5f * rho + 3.0f * mud);
+  const float half = 1.0f - 0.5f * itau;
+  const float uu = ux * ux + uy * uy + uz * uz;
+  const float gm3 = c.gamma3 * mu;
+  const float uf = ux * fx + uy * fy + uz * fz;
+  const float ug = ux * gpsx + uy * gpsy + uz * gpsz;
+  const float r3 = (1.0f / 3.0f) * rho;
+  float fsum = 0.0f;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const float eu = (EX(i) ? (EX(i) > 0 ? ux : -ux) : 0.0f) +
+                     (EY(i) ? (EY(i) > 0 ? uy : -uy) : 0.0f) +
+                     (EZ(i) ? (EZ(i) > 0 ? uz : -uz) : 0.0f);
+    const float ef = (EX(i) ? (EX(i) > 0 ? fx : -fx) : 0.0f) +
+                     (EY(i) ? (EY(i) > 0 ? fy : -fy) : 0.0f) +
+                     (EZ(i) ? (EZ(i) > 0 ? fz : -fz) : 0.0f);
+    const float eg = (EX(i) ? (EX(i) > 0 ? gpsx : -gpsx) : 0.0f) +
+                     (EY(i) ? (EY(i) > 0 ? gpsy : -gpsy) : 0.0f) +
+                     (EZ(i) ? (EZ(i) > 0 ? gpsz : -gpsz) : 0.0f);
+    const float ti = eu * (3.0f + 4.5f * eu) - 1.5f * uu;  // omega_i / w_i - 1
+    const float wt = WT(i) * ti;                           // omega_i - w_i
+    if (i > 0) {
+      const float feq = WT(i) * (gm3 + ph * ti);
+      const float fn = fv[i] - c.omega_f * (fv[i] - feq);
+      fsum += P::put_f(c, dst, i, idx, fn);
+    }
+    const float geq = WT(i) * p + r3 * wt;
+    const float src_i = (ef - uf) * (WT(i) + wt) - wt * (eg - ug);
+    const float gn = gv[i] - itau * (gv[i] - geq) + half * src_i;
+    P::put_g(c, dst, i, idx, gn, WT(i));
+  }
+  float h0, e0;
+  two_sum(phh, -fsum, h0, e0);
+  P::put_f0(c, dst, idx, h0, e0 + phl);
+}
+
+// ---- field dump for lbm_moments / diagnostics
+__global__ void __launch_bounds__(256) k3_dump(CaseDev c, Fields3 fl, FieldPtrs out) {
+  const unsigned idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (unsigned)c.n) return;
+  const float ux = fl.ux[idx], uy = fl.uy[idx], uz = fl.uz[idx], lmu = fl.lmu[idx];
+  out.phi[idx] = fl.phh[idx] + fl.phl[idx];
+  out.u[0][idx] = ux;
+  out.u[1][idx] = uy;
+  out.u[2][idx] = uz;
+  out.p[idx] = fl.p[idx];
+  out.mu[idx] = fl.mu[idx];
+  out.fa[0][idx] = -ux * c.fa_coef * lmu;
+  out.fa[1][idx] = -uy * c.fa_coef * lmu;
+  out.fa[2][idx] = -uz * c.fa_coef * lmu;
+}
+
+// ---- initial populations (inverse of the first pull)
+template <int S>
+__global__ void __launch_bounds__(256)
+k3_init(CaseDev c, int parity, const double* __restrict__ phi0, const double* __restrict__ u0,
+        const double* __restrict__ p0) {
+  using P = Pops<S, Q>;
+  const unsigned idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (unsigned)c.n) return;
+  int x, y, z;
+  coords(c, idx, x, y, z);
+  const double v0 = phi0[idx];
+  const float h0 = (float)v0, l0 = (float)(v0 - (double)h0);
+  float la = 0.0f, le = 0.0f;
+#pragma unroll
+  for (int i = 1; i < Q; ++i) {
+    const double v = phi0[nbr(c, x, y, z, i, false, idx)];
+    const float h = (float)v, l = (float)(v - (double)h);
+    const float d = (h - h0) + (l - l0);
+    if (i <= 6) la += d;
+    else le += d;
+  }
+  const float lap = (1.0f / 3.0f) * la + (1.0f / 6.0f) * le;
+  const float mu = dtheta(c, h0, l0) - c.kappa * lap;
+  const float ph = h0 + l0;
+  const unsigned n = c.n;
+  const float ux = (float)u0[idx], uy = (float)u0[n + idx], uz = (float)u0[2 * n + idx];
+  const float p = (float)p0[idx];
+  const float rho = c.rho_g + ph * c.drho;
+  const float uu = ux * ux + uy * uy + uz * uz;
+  char* dst = parity ? c.state[1] : c.state[0];
+  float fsum = 0.0f;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const float eu = EX(i) * ux + EY(i) * uy + EZ(i) * uz;
+    const float ti = 3.0f * eu + 4.5f * eu * eu - 1.5f * uu;
+    const float geq = WT(i) * p + (1.0f / 3.0f) * rho * WT(i) * ti;
+    int dir = i;
+    unsigned j = idx;
+    if (i > 0) {
+      bool bb;
+      const unsigned s = pull_src(c, x, y, z, EX(i), EY(i), EZ(i), &bb);
+      if (!bb) j = s;
+      else dir = OPP(i);
+      const float feq = WT(i) * (c.gamma3 * mu + ph * ti);
+      fsum += P::put_f(c, dst, dir, j, feq);
+    }
+    P::put_g(c, dst, dir, j, geq, WT(i));
+  }
+  float hh, ee;
+  two_sum(h0, -fsum, hh, ee);
+  P::put_f0(c, dst, idx, hh, ee + l0);
+}
+
+}  // namespace d3q19
+
+// ------------------------------------------------------------ launchers
+// One variant: node-parallel kernels of 256 threads (tile fields unused).
+const TileShape kD3Q19Tiles[] = {{1, 1, 1, 256}};
 const int kD3Q19TileCount = 1;
 
-hipError_t d3q19_step(int, const LaunchArgs&) { return hipErrorNotSupported; }
-hipError_t d3q19_fields(const LaunchArgs&, const FieldPtrs&) { return hipErrorNotSupported; }
-hipError_t d3q19_init(const CaseDev&, int, int, const double*, const double*, const double*,
-                      hipStream_t) {
-  return hipErrorNotSupported;
+namespace {
+d3q19::Fields3 fields3(const Field3Ptrs& f) {
+  d3q19::Fields3 fl;
+  fl.phh = f.plane[0];
+  fl.phl = f.plane[1];
+  fl.m0 = f.plane[2];
+  fl.m1x = f.plane[3];
+  fl.m1y = f.plane[4];
+  fl.m1z = f.plane[5];
+  fl.mu = f.plane[6];
+  fl.ux = f.plane[7];
+  fl.uy = f.plane[8];
+  fl.uz = f.plane[9];
+  fl.p = f.plane[10];
+  fl.lmu = f.plane[11];
+  fl.gx = f.plane[12];
+  fl.gy = f.plane[13];
+  fl.gz = f.plane[14];
+  return fl;
 }
+
+template <int S>
+hipError_t pipeline(const CaseDev& c, int parity, const d3q19::Fields3& fl, int want_lmu,
+                    bool collide, hipStream_t s) {
+  const int grid = (c.n + 255) / 256;
+  hipLaunchKernelGGL(d3q19::k3_pull<S>, dim3(grid), dim3(256), 0, s, c, parity, fl);
+  hipLaunchKernelGGL(d3q19::k3_mu, dim3(grid), dim3(256), 0, s, c, fl);
+  hipLaunchKernelGGL(d3q19::k3_fields, dim3(grid), dim3(256), 0, s, c, fl, want_lmu);
+  if (collide) hipLaunchKernelGGL(d3q19::k3_collide<S>, dim3(grid), dim3(256), 0, s, c, parity, fl);
+  return hipGetLastError();
+}
+}  // namespace
+
+hipError_t d3q19_step_case(const CaseDev& c, int storage, int parity, const Field3Ptrs& f,
+                           hipStream_t stream) {
+  const d3q19::Fields3 fl = fields3(f);
+  switch (storage) {
+    case ST_FP32: return pipeline<ST_FP32>(c, parity, fl, 0, true, stream);
+    case ST_FP16: return pipeline<ST_FP16>(c, parity, fl, 0, true, stream);
+    default: return pipeline<ST_BF16>(c, parity, fl, 0, true, stream);
+  }
+}
+
+hipError_t d3q19_fields_case(const CaseDev& c, int storage, int parity, const Field3Ptrs& f,
+                             const FieldPtrs& out, hipStream_t stream) {
+  const d3q19::Fields3 fl = fields3(f);
+  hipError_t e;
+  switch (storage) {
+    case ST_FP32: e = pipeline<ST_FP32>(c, parity, fl, 1, false, stream); break;
+    case ST_FP16: e = pipeline<ST_FP16>(c, parity, fl, 1, false, stream); break;
+    default: e = pipeline<ST_BF16>(c, parity, fl, 1, false, stream);
+  }
+  if (e != hipSuccess) return e;
+  const int grid = (c.n + 255) / 256;
+  hipLaunchKernelGGL(d3q19::k3_dump, dim3(grid), dim3(256), 0, stream, c, fl, out);
+  return hipGetLastError();
+}
+
+hipError_t d3q19_init(const CaseDev& c, int storage, int parity, const double* phi0,
+                      const double* u0, const double* p0, hipStream_t stream) {
+  const int grid = (c.n + 255) / 256;
+  switch (storage) {
+    case ST_FP32:
+      hipLaunchKernelGGL(d3q19::k3_init<ST_FP32>, dim3(grid), dim3(256), 0, stream, c, parity,
+                         phi0, u0, p0);
+      break;
+    case ST_FP16:
+      hipLaunchKernelGGL(d3q19::k3_init<ST_FP16>, dim3(grid), dim3(256), 0, stream, c, parity,
+                         phi0, u0, p0);
+      break;
+    default:
+      hipLaunchKernelGGL(d3q19::k3_init<ST_BF16>, dim3(grid), dim3(256), 0, stream, c, parity,
+                         phi0, u0, p0);
+  }
+  return hipGetLastError();
+}
+
 }  // namespace lbm

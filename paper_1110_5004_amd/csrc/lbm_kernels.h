@@ -43,8 +43,16 @@ hipError_t d2q9_fields(const LaunchArgs& a, const FieldPtrs& f);
 hipError_t d2q9_init(const CaseDev& c, int storage, int parity, const double* phi0,
                      const double* u0, const double* p0, hipStream_t stream);
 
-hipError_t d3q19_step(int variant, const LaunchArgs& a);
-hipError_t d3q19_fields(const LaunchArgs& a, const FieldPtrs& f);
+// D3Q19: four node-parallel kernels per case and step, passing 15 field
+// planes (phi hi/lo, gbar moments, mu, u, p, lap mu, grad phi).
+constexpr int kField3Planes = 15;
+struct Field3Ptrs {
+  float* plane[kField3Planes];
+};
+hipError_t d3q19_step_case(const CaseDev& c, int storage, int parity, const Field3Ptrs& f,
+                           hipStream_t stream);
+hipError_t d3q19_fields_case(const CaseDev& c, int storage, int parity, const Field3Ptrs& f,
+                             const FieldPtrs& out, hipStream_t stream);
 hipError_t d3q19_init(const CaseDev& c, int storage, int parity, const double* phi0,
                       const double* u0, const double* p0, hipStream_t stream);
 

@@ -183,9 +183,11 @@ Layout plan(const lbm_case_params* cs, int n) {
     nmax = std::max(nmax, stride_of(cs[k]));
   }
   // field scratch: phi, u (dim), p, mu, fa (dim) floats; also the staging of
-  // the FP64 initial fields (2 + dim doubles per node)
+  // the FP64 initial fields (2 + dim doubles per node).  D3Q19 steps also pass
+  // kField3Planes planes between their kernels, placed after the dump planes.
   L.fld_plane = (size_t)nmax;
-  const size_t fplanes = std::max<size_t>(3 + 2 * dim, 2 * (2 + dim));
+  size_t fplanes = std::max<size_t>(3 + 2 * dim, 2 * (2 + dim));
+  if (cs[0].lattice == LBM_D3Q19) fplanes = 3 + 2 * dim + lbm::kField3Planes;
   L.fld_off = at;
   at = align_up(at + fplanes * L.fld_plane * sizeof(float));
   L.part_off = at;
@@ -286,10 +288,23 @@ lbm::LaunchArgs step_args(lbm_handle* h, int parity, hipStream_t s) {
   return a;
 }
 
+lbm::Field3Ptrs step_fields3(lbm_handle* h) {
+  lbm::Field3Ptrs f{};
+  for (int k = 0; k < lbm::kField3Planes; ++k) f.plane[k] = h->fld(3 + 2 * h->dim + k);
+  return f;
+}
+
 hipError_t launch_step(lbm_handle* h, int parity, hipStream_t s) {
+  if (h->lattice == LBM_D3Q19) {
+    const lbm::Field3Ptrs f = step_fields3(h);
+    for (int k = 0; k < h->ncases; ++k) {
+      hipError_t e = lbm::d3q19_step_case(h->cd[k], h->storage, parity, f, s);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
   lbm::LaunchArgs a = step_args(h, parity, s);
-  return h->lattice == LBM_D3Q19 ? lbm::d3q19_step(h->variant, a)
-                                 : lbm::d2q9_step(h->variant, a);
+  return lbm::d2q9_step(h->variant, a);
 }
 
 int upload_tiles(lbm_handle* h) {
@@ -340,6 +355,11 @@ int ensure_graph(lbm_handle* h) {
 }
 
 int dump_fields(lbm_handle* h, int icase, const lbm::FieldPtrs& f) {
+  if (h->lattice == LBM_D3Q19) {
+    HIPCHK(lbm::d3q19_fields_case(h->cd[icase], h->storage, h->parity, step_fields3(h), f,
+                                  h->stream));
+    return LBM_OK;
+  }
   lbm::LaunchArgs a{};
   a.cases = h->d_cases();
   a.tiles = h->d_ftiles() + h->ftile_off[icase];
@@ -349,7 +369,7 @@ int dump_fields(lbm_handle* h, int icase, const lbm::FieldPtrs& f) {
   a.storage = h->storage;
   a.rf = 1;
   a.stream = h->stream;
-  HIPCHK(h->lattice == LBM_D3Q19 ? lbm::d3q19_fields(a, f) : lbm::d2q9_fields(a, f));
+  HIPCHK(lbm::d2q9_fields(a, f));
   return LBM_OK;
 }
 

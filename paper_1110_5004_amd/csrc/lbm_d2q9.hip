@@ -92,7 +92,7 @@ __device__ __forceinline__ void recover(const CaseDev& c, float phi, float gx, f
   const float fsx = mu * gx;
   const float fsy = mu * gy - (rho - c.rho_ref) * c.gravity;
   const float cc = c.corr * lmu;
-  const float iden = 1.0f / (rho - 0.5f * cc);
+  const float iden = __builtin_amdgcn_rcpf(rho - 0.5f * cc);
   ux = (3.0f * m1x + 0.5f * fsx) * iden;
   uy = (3.0f * m1y + 0.5f * fsy) * iden;
   p = m0 + (1.0f / 6.0f) * c.drho * (ux * gx + uy * gy);
@@ -253,21 +253,23 @@ __device__ __forceinline__ void ring_pos(int k, int& lx, int& ly) {
   }
 }
 
-// One tile, one node per thread (NT = TX * TY).  All global loads of the tile
-// are issued in one batch: the thread's own node keeps its 17 pulled
-// populations in registers for the collision; the rings around the tile pull
-// f for phi (radius R) and gbar for the moments (radius 1).
+// One tile, NPT nodes per thread (NT = TX * TY / NPT threads; node j of a
+// thread is tile position tid + j NT).  All global loads of the tile are
+// issued in one batch: a thread's own nodes keep their 17 pulled populations
+// in registers for the collision; the rings around the tile pull f for phi
+// (radius R) and gbar for the moments (radius 1).  Two nodes per thread
+// double the loads in flight per thread and halve the workgroups per tile.
 // INNER: every pulled population of the phi region lies inside the grid (no
 // wrap, no wall), so neighbours are plain index offsets.
-template <int TX, int TY, int RF, int S, bool FIELDS, bool INNER>
+template <int TX, int TY, int NPT, int RF, int S, bool FIELDS, bool INNER>
 __device__ __forceinline__ void tile_body(TileLds<TX, TY, RF>& L, const CaseDev& c, int x0, int y0,
                                           const char* src, char* dst, const FieldOut& fo) {
   using T = TileLds<TX, TY, RF>;
-  constexpr int NT = TX * TY;
+  constexpr int NT = TX * TY / NPT;   // threads; each owns NPT nodes of the tile
   constexpr int R = T::R, RM = T::RM;
   constexpr int PW = T::PW, PH = T::PH, MW = T::MW, MH = T::MH, UW = T::UW, UH = T::UH;
-  constexpr int NRA = PW * PH - NT;   // phi ring
-  constexpr int NRC = UW * UH - NT;   // moment ring
+  constexpr int NRA = PW * PH - TX * TY;   // phi ring
+  constexpr int NRC = UW * UH - TX * TY;   // moment ring
   constexpr int IA = (NRA + NT - 1) / NT;
   constexpr int IB = (MW * MH + NT - 1) / NT;
   constexpr int IC = (NRC + NT - 1) / NT;
@@ -277,21 +279,22 @@ __device__ __forceinline__ void tile_body(TileLds<TX, TY, RF>& L, const CaseDev&
   const int tid = threadIdx.x;
   const int nx = c.nx, ny = c.ny;
   const InnerPtrs<S> ip(c, src);
+  const OutPtrs<S, Q> op(c, dst);
 
-  // ---- A: loads.  Own node: f_1..f_8, gbar_0..gbar_8 in registers, phi and
+  // ---- A: loads.  Own nodes: f_1..f_8, gbar_0..gbar_8 in registers, phi and
   // the gbar moments to LDS.  Rings: phi and moments of halo positions.
-  const int lx0 = tid % TX, ly0 = tid / TX;
-  const int gx0 = x0 + lx0, gy0 = y0 + ly0;
-  const bool own_real = INNER || (gx0 < nx && gy0 < ny);
-  float fv[Q], gv[Q];
-  {
-    int mx = gx0, my = gy0;
+  float fv[NPT][Q], gv[NPT][Q];
+#pragma unroll
+  for (int j = 0; j < NPT; ++j) {
+    const int kk = tid + j * NT;
+    const int lx0 = kk % TX, ly0 = kk / TX;
+    int mx = x0 + lx0, my = y0 + ly0;
     if constexpr (!INNER) {
-      mx = map_axis(gx0, nx, c.wall_x);
-      my = map_axis(gy0, ny, c.wall_y);
+      mx = map_axis(mx, nx, c.wall_x);
+      my = map_axis(my, ny, c.wall_y);
     }
     const unsigned idx = mx + nx * my;
-    pull_all<S, INNER>(c, src, ip, mx, my, idx, fv, gv);
+    pull_all<S, INNER>(c, src, ip, mx, my, idx, fv[j], gv[j]);
     float f0, f0l;
     if constexpr (INNER) {
       f0 = ip.fv(c, 0, idx);
@@ -302,7 +305,7 @@ __device__ __forceinline__ void tile_body(TileLds<TX, TY, RF>& L, const CaseDev&
     }
     float sm = 0.0f;
 #pragma unroll
-    for (int i = 1; i < Q; ++i) sm += fv[i];
+    for (int i = 1; i < Q; ++i) sm += fv[j][i];
     float hi, lo;
     two_sum(f0, f0l + sm, hi, lo);
     const int pk = (ly0 + R) * PW + (lx0 + R);
@@ -311,9 +314,9 @@ __device__ __forceinline__ void tile_body(TileLds<TX, TY, RF>& L, const CaseDev&
     float m0 = 0.0f, m1x = 0.0f, m1y = 0.0f;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-      m0 += gv[i];
-      if (EX(i)) m1x += EX(i) > 0 ? gv[i] : -gv[i];
-      if (EY(i)) m1y += EY(i) > 0 ? gv[i] : -gv[i];
+      m0 += gv[j][i];
+      if (EX(i)) m1x += EX(i) > 0 ? gv[j][i] : -gv[j][i];
+      if (EY(i)) m1y += EY(i) > 0 ? gv[j][i] : -gv[j][i];
     }
     const int uk = (ly0 + 1) * UW + (lx0 + 1);
     L.p[uk] = m0;
@@ -403,8 +406,13 @@ __device__ __forceinline__ void tile_body(TileLds<TX, TY, RF>& L, const CaseDev&
   }
   __syncthreads();
 
-  // ---- D: collide (or dump fields) the own node
-  if (own_real) {
+  // ---- D: collide (or dump fields) the own nodes
+#pragma unroll
+  for (int j = 0; j < NPT; ++j) {
+    const int kk = tid + j * NT;
+    const int lx0 = kk % TX, ly0 = kk / TX;
+    const int gx0 = x0 + lx0, gy0 = y0 + ly0;
+    if (!(INNER || (gx0 < nx && gy0 < ny))) continue;
     const unsigned idx = gx0 + nx * gy0;
     const int pc = (ly0 + R) * PW + (lx0 + R);
     const int mx = lx0 + RM, my = ly0 + RM;
@@ -436,42 +444,50 @@ __device__ __forceinline__ void tile_body(TileLds<TX, TY, RF>& L, const CaseDev&
       grad_only<UW>(L.p, lx0 + 1, ly0 + 1, gpx, gpy);
       const float gpsx = gpx - (1.0f / 3.0f) * c.drho * gx;
       const float gpsy = gpy - (1.0f / 3.0f) * c.drho * gy;
-      // tau = 1/2 + 3 nu, nu = mu_dyn(phi) / rho  ->  1/tau in one division
+      // tau = 1/2 + 3 nu, nu = mu_dyn(phi) / rho
       const float mud = c.mu_g + ph * c.dmu;
-      const float itau = rho / (0.5f * rho + 3.0f * mud);
-      const float half = 1.0f - 0.5f * itau;
+      const float om = rho * __builtin_amdgcn_rcpf(0.5f * rho + 3.0f * mud);  // 1 / tau
+      const float half = 1.0f - 0.5f * om;
       const float uu = ux * ux + uy * uy;
-      const float gm3 = c.gamma3 * mu;
-      const float uf = ux * fx + uy * fy;        // u . F
-      const float ug = ux * gpsx + uy * gpsy;    // u . grad psi
-      const float r3 = (1.0f / 3.0f) * rho;
+      // BGK with the Eq. 8 forcing, regrouped per direction as
+      //   g* = (1 - om) g + w [A + B_i + t_i (C + D_i)]
+      // with t_i = omega_i / w_i - 1, g^eq = w p + (rho/3) w t_i,
+      // S_i = w [(e.F - u.F)(1 + t_i) - t_i (e.grad psi - u.grad psi)]:
+      //   A = om p - half u.F,  C = om rho/3 - half u.F + half u.grad psi,
+      //   B_i = half e.F,  D_i = half e.(F - grad psi);
+      // and f* = (1 - om_f) f + w (om_f 3 Gamma mu + om_f phi t_i).
+      const float uf = ux * fx + uy * fy;
+      const float ug = ux * gpsx + uy * gpsy;
+      const float A = om * p - half * uf;
+      const float Cc = om * (1.0f / 3.0f) * rho - half * uf + half * ug;
+      const float hfx = half * fx, hfy = half * fy;
+      const float hdx = half * (fx - gpsx), hdy = half * (fy - gpsy);
+      const float m15 = -1.5f * uu;
+      const float omg = 1.0f - om;
+      const float omf = 1.0f - c.omega_f;
+      const float fP = c.omega_f * c.gamma3 * mu;
+      const float fQ = c.omega_f * ph;
       float fsum = 0.0f;
 #pragma unroll
       for (int i = 0; i < Q; ++i) {
         // e_i . v for e_i with components in {-1, 0, 1}
         const float eu = (EX(i) ? (EX(i) > 0 ? ux : -ux) : 0.0f) +
                          (EY(i) ? (EY(i) > 0 ? uy : -uy) : 0.0f);
-        const float ef = (EX(i) ? (EX(i) > 0 ? fx : -fx) : 0.0f) +
-                         (EY(i) ? (EY(i) > 0 ? fy : -fy) : 0.0f);
-        const float eg = (EX(i) ? (EX(i) > 0 ? gpsx : -gpsx) : 0.0f) +
-                         (EY(i) ? (EY(i) > 0 ? gpsy : -gpsy) : 0.0f);
-        const float ti = eu * (3.0f + 4.5f * eu) - 1.5f * uu;  // omega_i / w_i - 1
-        const float wt = WT(i) * ti;                           // omega_i - w_i
+        const float bi = (EX(i) ? (EX(i) > 0 ? hfx : -hfx) : 0.0f) +
+                         (EY(i) ? (EY(i) > 0 ? hfy : -hfy) : 0.0f);
+        const float di = (EX(i) ? (EX(i) > 0 ? hdx : -hdx) : 0.0f) +
+                         (EY(i) ? (EY(i) > 0 ? hdy : -hdy) : 0.0f);
+        const float ti = eu * (3.0f + 4.5f * eu) + m15;  // omega_i / w_i - 1
         if (i > 0) {
-          const float feq = WT(i) * (gm3 + ph * ti);
-          const float fn = fv[i] - c.omega_f * (fv[i] - feq);
-          fsum += P::put_f(c, dst, i, idx, fn);
+          const float fn = omf * fv[j][i] + WT(i) * (fP + fQ * ti);
+          fsum += op.put_f(c, i, idx, fn);
         }
-        // g^eq = w p + rho cs^2 (omega - w);
-        // S = (e - u).[F omega - (omega - w) grad psi]
-        const float geq = WT(i) * p + r3 * wt;
-        const float src_i = (ef - uf) * (WT(i) + wt) - wt * (eg - ug);
-        const float gn = gv[i] - itau * (gv[i] - geq) + half * src_i;
-        P::put_g(c, dst, i, idx, gn, WT(i));
+        const float gn = omg * gv[j][i] + WT(i) * ((A + bi) + ti * (Cc + di));
+        op.put_g(c, i, idx, gn, WT(i));
       }
       float h0, e0;
       two_sum(phh, -fsum, h0, e0);
-      P::put_f0(c, dst, idx, h0, e0 + phl);
+      op.put_f0(idx, h0, e0 + phl);
     }
   }
   __syncthreads();
@@ -480,8 +496,9 @@ __device__ __forceinline__ void tile_body(TileLds<TX, TY, RF>& L, const CaseDev&
 // RF = 1: lap mu is formed (corrected model, or the F_a dump); phi halo 3.
 // WPE > 0 asks the compiler for at least that many waves per SIMD (fewer
 // registers, more tiles in flight per CU).
-template <int TX, int TY, int RF, int S, bool FIELDS, int WPE>
-__global__ void __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(WPE > 0 ? WPE : 1)))
+template <int TX, int TY, int NPT, int RF, int S, bool FIELDS, int WPE>
+__global__ void __launch_bounds__(TX * TY / NPT)
+__attribute__((amdgpu_waves_per_eu(WPE > 0 ? WPE : 1)))
 k_tile(const CaseDev* __restrict__ cases, const TileDev* __restrict__ tiles, int ntiles,
        int parity, FieldOut fo) {
   constexpr int R = TileLds<TX, TY, RF>::R;
@@ -502,9 +519,9 @@ k_tile(const CaseDev* __restrict__ cases, const TileDev* __restrict__ tiles, int
     const bool inner = (tl.x0 - R - 1 >= 0) && (tl.x0 + TX + R + 1 <= c.nx) &&
                        (tl.y0 - R - 1 >= 0) && (tl.y0 + TY + R + 1 <= c.ny);
     if (inner)
-      tile_body<TX, TY, RF, S, FIELDS, true>(lds, c, tl.x0, tl.y0, src, dst, fo);
+      tile_body<TX, TY, NPT, RF, S, FIELDS, true>(lds, c, tl.x0, tl.y0, src, dst, fo);
     else
-      tile_body<TX, TY, RF, S, FIELDS, false>(lds, c, tl.x0, tl.y0, src, dst, fo);
+      tile_body<TX, TY, NPT, RF, S, FIELDS, false>(lds, c, tl.x0, tl.y0, src, dst, fo);
   }
 }
 
@@ -570,45 +587,45 @@ k_init(CaseDev c, int parity, const double* __restrict__ phi0, const double* __r
 namespace {
 using d2q9::FieldOut;
 
-template <int TX, int TY, int RF, int S, int WPE>
+template <int TX, int TY, int NPT, int RF, int S, int WPE>
 hipError_t launch_step_t(const LaunchArgs& a) {
   FieldOut fo{};
-  hipLaunchKernelGGL((d2q9::k_tile<TX, TY, RF, S, false, WPE>), dim3(a.grid), dim3(TX * TY), 0,
-                     a.stream, a.cases, a.tiles, a.ntiles, a.parity, fo);
+  hipLaunchKernelGGL((d2q9::k_tile<TX, TY, NPT, RF, S, false, WPE>), dim3(a.grid),
+                     dim3(TX * TY / NPT), 0, a.stream, a.cases, a.tiles, a.ntiles, a.parity, fo);
   return hipGetLastError();
 }
 
 template <int TX, int TY, int S>
 hipError_t launch_fields_t(const LaunchArgs& a, const FieldPtrs& f) {
   FieldOut fo{f.phi, f.u[0], f.u[1], f.u[2], f.p, f.mu, f.fa[0], f.fa[1], f.fa[2]};
-  hipLaunchKernelGGL((d2q9::k_tile<TX, TY, 1, S, true, 0>), dim3(a.grid), dim3(TX * TY), 0,
+  hipLaunchKernelGGL((d2q9::k_tile<TX, TY, 1, 1, S, true, 0>), dim3(a.grid), dim3(TX * TY), 0,
                      a.stream, a.cases, a.tiles, a.ntiles, a.parity, fo);
   return hipGetLastError();
 }
 
-template <int TX, int TY, int WPE = 0>
+template <int TX, int TY, int NPT = 1, int WPE = 0>
 hipError_t launch_step_v(const LaunchArgs& a) {
   if (a.rf) {
     switch (a.storage) {
-      case ST_FP32: return launch_step_t<TX, TY, 1, ST_FP32, WPE>(a);
-      case ST_FP16: return launch_step_t<TX, TY, 1, ST_FP16, WPE>(a);
-      default: return launch_step_t<TX, TY, 1, ST_BF16, WPE>(a);
+      case ST_FP32: return launch_step_t<TX, TY, NPT, 1, ST_FP32, WPE>(a);
+      case ST_FP16: return launch_step_t<TX, TY, NPT, 1, ST_FP16, WPE>(a);
+      default: return launch_step_t<TX, TY, NPT, 1, ST_BF16, WPE>(a);
     }
   }
   switch (a.storage) {
-    case ST_FP32: return launch_step_t<TX, TY, 0, ST_FP32, WPE>(a);
-    case ST_FP16: return launch_step_t<TX, TY, 0, ST_FP16, WPE>(a);
-    default: return launch_step_t<TX, TY, 0, ST_BF16, WPE>(a);
+    case ST_FP32: return launch_step_t<TX, TY, NPT, 0, ST_FP32, WPE>(a);
+    case ST_FP16: return launch_step_t<TX, TY, NPT, 0, ST_FP16, WPE>(a);
+    default: return launch_step_t<TX, TY, NPT, 0, ST_BF16, WPE>(a);
   }
 }
 }  // namespace
 
-// Compiled tile shapes of the D2Q9 step (index = launch variant); one node
-// per thread.
+// Compiled tile shapes of the D2Q9 step (index = launch variant): tile width,
+// height, depth and threads per workgroup (one or two nodes per thread).
 const TileShape kD2Q9Tiles[] = {{32, 16, 1, 512}, {64, 8, 1, 512},  {64, 16, 1, 1024},
-                                {32, 8, 1, 256},  {128, 4, 1, 512}, {256, 4, 1, 1024},
-                                {64, 8, 1, 512},  {128, 4, 1, 512}, {32, 16, 1, 512},
-                                {64, 8, 1, 512}};
+                                {32, 8, 1, 256},  {128, 4, 1, 512}, {64, 8, 1, 512},
+                                {64, 16, 1, 512}, {32, 16, 1, 256}, {64, 8, 1, 256},
+                                {128, 8, 1, 512}};
 const int kD2Q9TileCount = sizeof(kD2Q9Tiles) / sizeof(kD2Q9Tiles[0]);
 
 hipError_t d2q9_step(int variant, const LaunchArgs& a) {
@@ -618,11 +635,11 @@ hipError_t d2q9_step(int variant, const LaunchArgs& a) {
     case 2: return launch_step_v<64, 16>(a);
     case 3: return launch_step_v<32, 8>(a);
     case 4: return launch_step_v<128, 4>(a);
-    case 5: return launch_step_v<256, 4>(a);
-    case 6: return launch_step_v<64, 8, 8>(a);
-    case 7: return launch_step_v<128, 4, 8>(a);
-    case 8: return launch_step_v<32, 16, 8>(a);
-    case 9: return launch_step_v<64, 8, 6>(a);
+    case 5: return launch_step_v<64, 8, 1, 6>(a);
+    case 6: return launch_step_v<64, 16, 2>(a);
+    case 7: return launch_step_v<32, 16, 2>(a);
+    case 8: return launch_step_v<64, 8, 2>(a);
+    case 9: return launch_step_v<128, 8, 2>(a);
     default: return hipErrorInvalidValue;
   }
 }

@@ -183,7 +183,7 @@ __global__ void __launch_bounds__(256) k3_fields(CaseDev c, Fields3 fl, int want
   const float fsx = mu * g[0], fsy = mu * g[1];
   const float fsz = mu * g[2] - (rho - c.rho_ref) * c.gravity;
   const float cc = c.corr * lmu;
-  const float iden = 1.0f / (rho - 0.5f * cc);
+  const float iden = __builtin_amdgcn_rcpf(rho - 0.5f * cc);
   const float ux = (3.0f * fl.m1x[idx] + 0.5f * fsx) * iden;
   const float uy = (3.0f * fl.m1y[idx] + 0.5f * fsy) * iden;
   const float uz = (3.0f * fl.m1z[idx] + 0.5f * fsz) * iden;
@@ -208,6 +208,7 @@ __global__ void __launch_bounds__(256) k3_collide(CaseDev c, int parity, Fields3
   const bool in = is_interior(c, x, y, z);
   const char* src = parity ? c.state[1] : c.state[0];
   char* dst = parity ? c.state[0] : c.state[1];
+  const OutPtrs<S, Q> op(c, dst);
   float fv[Q], gv[Q];
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
@@ -230,40 +231,45 @@ __global__ void __launch_bounds__(256) k3_collide(CaseDev c, int parity, Fields3
   const float gpsy = gp[1] - (1.0f / 3.0f) * c.drho * gy;
   const float gpsz = gp[2] - (1.0f / 3.0f) * c.drho * gz;
   const float mud = c.mu_g + ph * c.dmu;
-  const float itau = rho / (0.5f * rho + 3.0f * mud);
-  const float half = 1.0f - 0.5f * itau;
+  const float om = rho * __builtin_amdgcn_rcpf(0.5f * rho + 3.0f * mud);  // 1 / tau
+  const float half = 1.0f - 0.5f * om;
   const float uu = ux * ux + uy * uy + uz * uz;
-  const float gm3 = c.gamma3 * mu;
+  // regrouped BGK with the Eq. 8 forcing (see the D2Q9 step):
+  //   g* = (1 - om) g + w [A + B_i + t_i (C + D_i)],  f* = (1 - om_f) f + w (P + Q t_i)
   const float uf = ux * fx + uy * fy + uz * fz;
   const float ug = ux * gpsx + uy * gpsy + uz * gpsz;
-  const float r3 = (1.0f / 3.0f) * rho;
+  const float A = om * p - half * uf;
+  const float Cc = om * (1.0f / 3.0f) * rho - half * uf + half * ug;
+  const float hfx = half * fx, hfy = half * fy, hfz = half * fz;
+  const float hdx = half * (fx - gpsx), hdy = half * (fy - gpsy), hdz = half * (fz - gpsz);
+  const float m15 = -1.5f * uu;
+  const float omg = 1.0f - om;
+  const float omf = 1.0f - c.omega_f;
+  const float fP = c.omega_f * c.gamma3 * mu;
+  const float fQ = c.omega_f * ph;
   float fsum = 0.0f;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     const float eu = (EX(i) ? (EX(i) > 0 ? ux : -ux) : 0.0f) +
                      (EY(i) ? (EY(i) > 0 ? uy : -uy) : 0.0f) +
                      (EZ(i) ? (EZ(i) > 0 ? uz : -uz) : 0.0f);
-    const float ef = (EX(i) ? (EX(i) > 0 ? fx : -fx) : 0.0f) +
-                     (EY(i) ? (EY(i) > 0 ? fy : -fy) : 0.0f) +
-                     (EZ(i) ? (EZ(i) > 0 ? fz : -fz) : 0.0f);
-    const float eg = (EX(i) ? (EX(i) > 0 ? gpsx : -gpsx) : 0.0f) +
-                     (EY(i) ? (EY(i) > 0 ? gpsy : -gpsy) : 0.0f) +
-                     (EZ(i) ? (EZ(i) > 0 ? gpsz : -gpsz) : 0.0f);
-    const float ti = eu * (3.0f + 4.5f * eu) - 1.5f * uu;  // omega_i / w_i - 1
-    const float wt = WT(i) * ti;                           // omega_i - w_i
+    const float bi = (EX(i) ? (EX(i) > 0 ? hfx : -hfx) : 0.0f) +
+                     (EY(i) ? (EY(i) > 0 ? hfy : -hfy) : 0.0f) +
+                     (EZ(i) ? (EZ(i) > 0 ? hfz : -hfz) : 0.0f);
+    const float di = (EX(i) ? (EX(i) > 0 ? hdx : -hdx) : 0.0f) +
+                     (EY(i) ? (EY(i) > 0 ? hdy : -hdy) : 0.0f) +
+                     (EZ(i) ? (EZ(i) > 0 ? hdz : -hdz) : 0.0f);
+    const float ti = eu * (3.0f + 4.5f * eu) + m15;
     if (i > 0) {
-      const float feq = WT(i) * (gm3 + ph * ti);
-      const float fn = fv[i] - c.omega_f * (fv[i] - feq);
-      fsum += P::put_f(c, dst, i, idx, fn);
+      const float fn = omf * fv[i] + WT(i) * (fP + fQ * ti);
+      fsum += op.put_f(c, i, idx, fn);
     }
-    const float geq = WT(i) * p + r3 * wt;
-    const float src_i = (ef - uf) * (WT(i) + wt) - wt * (eg - ug);
-    const float gn = gv[i] - itau * (gv[i] - geq) + half * src_i;
-    P::put_g(c, dst, i, idx, gn, WT(i));
+    const float gn = omg * gv[i] + WT(i) * ((A + bi) + ti * (Cc + di));
+    op.put_g(c, i, idx, gn, WT(i));
   }
   float h0, e0;
   two_sum(phh, -fsum, h0, e0);
-  P::put_f0(c, dst, idx, h0, e0 + phl);
+  op.put_f0(idx, h0, e0 + phl);
 }
 
 // ---- field dump for lbm_moments / diagnostics

@@ -181,6 +181,51 @@ struct Pops {
   }
 };
 
+// Uniform per-plane destination pointers of one copy: every store of a node
+// then uses the same per-lane offset (4 idx for float planes, 2 idx for
+// 16-bit planes).
+template <int S, int Q>
+struct OutPtrs {
+  char* f[Q];
+  char* g[Q];
+  char* f0lo;
+  __device__ __forceinline__ OutPtrs(const CaseDev& c, char* base) {
+    using P = Pops<S, Q>;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      f[i] = base + P::fofs(c, i, 0);
+      g[i] = base + P::gofs(c, i, 0);
+    }
+    f0lo = base + (size_t)(2 * Q) * 4 * c.stride;
+  }
+  // store f_i (i > 0) at node idx; returns what was stored (decoded)
+  __device__ __forceinline__ float put_f(const CaseDev& c, int i, unsigned idx, float v) const {
+    if constexpr (S == ST_FP32) {
+      gstore<float>(f[i], 4u * idx, v);
+      return v;
+    } else {
+      const uint16_t h = enc16<S>(v * c.scale_f);
+      gstore<uint16_t>(f[i], 2u * idx, h);
+      return dec16<S>(h) * c.inv_scale_f;
+    }
+  }
+  __device__ __forceinline__ void put_g(const CaseDev& c, int i, unsigned idx, float v,
+                                        float wi) const {
+    if constexpr (S == ST_FP32) gstore<float>(g[i], 4u * idx, v);
+    else gstore<uint16_t>(g[i], 2u * idx, enc16<S>((v - wi * c.p0) * c.scale_g));
+  }
+  __device__ __forceinline__ void put_f0(unsigned idx, float hi, float lo) const {
+    if constexpr (S == ST_FP32) {
+      float h, l;
+      two_sum(hi, lo, h, l);
+      gstore<float>(f[0], 4u * idx, h);
+      gstore<uint16_t>(f0lo, 2u * idx, enc_bf16(l));
+    } else {
+      gstore<float>(f[0], 4u * idx, hi + lo);
+    }
+  }
+};
+
 // Coordinate of a stencil position on one axis: periodic wrap, or the mirror
 // ghost of a wall half a cell beyond the last node (ghost -k <-> node k-1),
 // clamped so that positions far outside (never used by a real node) still

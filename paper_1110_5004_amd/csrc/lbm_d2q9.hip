@@ -98,6 +98,10 @@ __device__ __forceinline__ void recover(const CaseDev& c, float phi, float gx, f
   p = m0 + (1.0f / 6.0f) * c.drho * (ux * gx + uy * gy);
 }
 
+// Stored word of f_i (i > 0) and of g_i: a float, or 16 bits.
+template <int S>
+using Raw = typename std::conditional<S == ST_FP32, float, uint16_t>::type;
+
 // Interior tiles: per-direction uniform base pointers already shifted by
 // -e_i, so that every pulled population of node idx is base_i[idx] and all
 // loads of a node share one per-lane offset.
@@ -117,19 +121,6 @@ struct InnerPtrs {
       g[i] = src + P::gofs(c, i, 0) - (long)sh * gw;
     }
     f0lo = src + (size_t)(2 * Q) * 4 * c.stride;
-  }
-  __device__ __forceinline__ float fv(const CaseDev& c, int i, unsigned idx) const {
-    if constexpr (S == ST_FP32) return gload<float>(f[i], 4u * idx);
-    else if (i == 0) return gload<float>(f[0], 4u * idx);
-    else return dec16<S>(gload<uint16_t>(f[i], 2u * idx)) * c.inv_scale_f;
-  }
-  __device__ __forceinline__ float gv(const CaseDev& c, int i, unsigned idx) const {
-    if constexpr (S == ST_FP32) return gload<float>(g[i], 4u * idx);
-    else return dec16<S>(gload<uint16_t>(g[i], 2u * idx)) * c.inv_scale_g + WT(i) * c.p0;
-  }
-  __device__ __forceinline__ float lo(unsigned idx) const {
-    if constexpr (S == ST_FP32) return dec_bf16(gload<uint16_t>(f0lo, 2u * idx));
-    else return 0.0f;
   }
 };
 
@@ -152,57 +143,65 @@ __device__ __forceinline__ unsigned pull_ofs(const CaseDev& c, int x, int y, uns
   }
 }
 
-// phi = f_0 + sum_{i>0} f_i as hi + lo (pulled populations).
+// Raw loads of the populations a node pulls.  FV: f_0, its low part and
+// f_1..f_8; GV: gbar_0..gbar_8.
 template <int S, bool INNER>
-__device__ __forceinline__ void phi_pull(const CaseDev& c, const char* src,
-                                         const InnerPtrs<S>& ip, int x, int y, float& hi,
-                                         float& lo) {
-  using P = Pops<S, Q>;
-  const unsigned idx = x + c.nx * y;
-  float sm = 0.0f;
-  if constexpr (INNER) {
+struct Puller {
+  const CaseDev& c;
+  const char* src;
+  InnerPtrs<S> ip;
+  __device__ __forceinline__ Puller(const CaseDev& cc, const char* s) : c(cc), src(s), ip(cc, s) {}
+  __device__ __forceinline__ void fpop(int x, int y, float& f0, uint16_t& lo, Raw<S>* fr) const {
+    using P = Pops<S, Q>;
+    const unsigned idx = x + c.nx * y;
+    constexpr unsigned W = sizeof(Raw<S>);
 #pragma unroll
-    for (int i = 1; i < Q; ++i) sm += ip.fv(c, i, idx);
-    two_sum(ip.fv(c, 0, idx), ip.lo(idx) + sm, hi, lo);
-  } else {
-#pragma unroll
-    for (int i = 1; i < Q; ++i) sm += P::f(c, src, i, pull_ofs<S, false, false>(c, x, y, idx, i));
-    two_sum(P::f(c, src, 0, P::fofs(c, 0, idx)), P::f0lo(c, src, idx) + sm, hi, lo);
+    for (int i = 1; i < Q; ++i) {
+      if constexpr (INNER) fr[i] = gload<Raw<S>>(ip.f[i], W * idx);
+      else fr[i] = gload<Raw<S>>(src, pull_ofs<S, false, false>(c, x, y, idx, i));
+    }
+    f0 = INNER ? gload<float>(ip.f[0], 4u * idx) : gload<float>(src, P::fofs(c, 0, idx));
+    if constexpr (S == ST_FP32) lo = gload<uint16_t>(ip.f0lo, 2u * idx);
+    else lo = 0;
   }
+  __device__ __forceinline__ void gpop(int x, int y, Raw<S>* gr) const {
+    const unsigned idx = x + c.nx * y;
+    constexpr unsigned W = sizeof(Raw<S>);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      if constexpr (INNER) gr[i] = gload<Raw<S>>(ip.g[i], W * idx);
+      else gr[i] = gload<Raw<S>>(src, pull_ofs<S, false, true>(c, x, y, idx, i));
+    }
+  }
+};
+
+// phi = f_0 + sum_{i>0} f_i as hi + lo, from raw pulled words.
+template <int S>
+__device__ __forceinline__ void phi_sum(const CaseDev& c, float f0, uint16_t lo,
+                                        const Raw<S>* fr, float* fv, float& hi, float& plo) {
+  using P = Pops<S, Q>;
+  float sm = 0.0f;
+#pragma unroll
+  for (int i = 1; i < Q; ++i) {
+    fv[i] = P::dec_f(c, fr[i]);
+    sm += fv[i];
+  }
+  two_sum(f0, P::dec_lo(lo) + sm, hi, plo);
 }
 
-template <int S, bool INNER>
-__device__ __forceinline__ void g_moments(const CaseDev& c, const char* src,
-                                          const InnerPtrs<S>& ip, int x, int y, float& m0,
-                                          float& m1x, float& m1y) {
+// Zeroth and first moments of gbar from raw pulled words.
+template <int S>
+__device__ __forceinline__ void g_sum(const CaseDev& c, const Raw<S>* gr, float* gv, float& m0,
+                                      float& m1x, float& m1y) {
   using P = Pops<S, Q>;
-  const unsigned idx = x + c.nx * y;
   m0 = m1x = m1y = 0.0f;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    const float v = INNER ? ip.gv(c, i, idx)
-                          : P::g(c, src, pull_ofs<S, false, true>(c, x, y, idx, i), WT(i));
+    const float v = P::dec_g(c, gr[i], WT(i));
+    gv[i] = v;
     m0 += v;
     if (EX(i)) m1x += EX(i) > 0 ? v : -v;
     if (EY(i)) m1y += EY(i) > 0 ? v : -v;
-  }
-}
-
-// Every population pulled by one node: f_1..f_8 and g_0..g_8.
-template <int S, bool INNER>
-__device__ __forceinline__ void pull_all(const CaseDev& c, const char* src,
-                                         const InnerPtrs<S>& ip, int x, int y, unsigned idx,
-                                         float* fv, float* gv) {
-  using P = Pops<S, Q>;
-#pragma unroll
-  for (int i = 0; i < Q; ++i) {
-    if constexpr (INNER) {
-      if (i > 0) fv[i] = ip.fv(c, i, idx);
-      gv[i] = ip.gv(c, i, idx);
-    } else {
-      if (i > 0) fv[i] = P::f(c, src, i, pull_ofs<S, false, false>(c, x, y, idx, i));
-      gv[i] = P::g(c, src, pull_ofs<S, false, true>(c, x, y, idx, i), WT(i));
-    }
   }
 }
 
@@ -232,6 +231,9 @@ struct TileLds {
   float ux[UW * UH];  // first moments of gbar, then u
   float uy[UW * UH];
   float p[UW * UH];   // zeroth moment of gbar, then p
+  float gx[TX * TY];  // grad phi and lap mu of the tile nodes, kept from C for D
+  float gy[TX * TY];
+  float lm[TX * TY];
 };
 
 // Position k of the ring of width r around a TX x TY tile inside a region
@@ -253,112 +255,155 @@ __device__ __forceinline__ void ring_pos(int k, int& lx, int& ly) {
   }
 }
 
-// One tile, NPT nodes per thread (NT = TX * TY / NPT threads; node j of a
-// thread is tile position tid + j NT).  All global loads of the tile are
-// issued in one batch: a thread's own nodes keep their 17 pulled populations
-// in registers for the collision; the rings around the tile pull f for phi
-// (radius R) and gbar for the moments (radius 1).  Two nodes per thread
-// double the loads in flight per thread and halve the workgroups per tile.
-// INNER: every pulled population of the phi region lies inside the grid (no
-// wrap, no wall), so neighbours are plain index offsets.
-template <int TX, int TY, int NPT, int RF, int S, bool FIELDS, bool INNER>
-__device__ __forceinline__ void tile_body(TileLds<TX, TY, RF>& L, const CaseDev& c, int x0, int y0,
-                                          const char* src, char* dst, const FieldOut& fo) {
+// Everything one tile loads from global memory, held in registers as stored
+// words between issue (loads in flight) and consume (sums into LDS).  One
+// tile has NT = TX * TY / NPT threads; node j of a thread is tile position
+// tid + j NT.  Rings around the tile: phi at radius R (f pulled) and the
+// gbar moments at radius 1.
+template <int TX, int TY, int NPT, int RF, int S>
+struct TileLoads {
   using T = TileLds<TX, TY, RF>;
-  constexpr int NT = TX * TY / NPT;   // threads; each owns NPT nodes of the tile
-  constexpr int R = T::R, RM = T::RM;
-  constexpr int PW = T::PW, PH = T::PH, MW = T::MW, MH = T::MH, UW = T::UW, UH = T::UH;
-  constexpr int NRA = PW * PH - TX * TY;   // phi ring
-  constexpr int NRC = UW * UH - TX * TY;   // moment ring
-  constexpr int IA = (NRA + NT - 1) / NT;
-  constexpr int IB = (MW * MH + NT - 1) / NT;
-  constexpr int IC = (NRC + NT - 1) / NT;
-  constexpr int ICC = (UW * UH + NT - 1) / NT;
-  using P = Pops<S, Q>;
-  const FF<PW> phi{L.ph, L.pl};
-  const int tid = threadIdx.x;
-  const int nx = c.nx, ny = c.ny;
-  const InnerPtrs<S> ip(c, src);
-  const OutPtrs<S, Q> op(c, dst);
+  static constexpr int NT = TX * TY / NPT;
+  static constexpr int R = T::R;
+  static constexpr int NRA = T::PW * T::PH - TX * TY;  // phi ring
+  static constexpr int NRC = T::UW * T::UH - TX * TY;  // moment ring
+  static constexpr int IA = (NRA + NT - 1) / NT;
+  static constexpr int IC = (NRC + NT - 1) / NT;
+  float f0[NPT];
+  uint16_t lo[NPT];
+  Raw<S> fr[NPT][Q];
+  Raw<S> gr[NPT][Q];
+  float af0[IA];
+  uint16_t alo[IA];
+  Raw<S> afr[IA][Q];
+  Raw<S> cgr[IC][Q];
 
-  // ---- A: loads.  Own nodes: f_1..f_8, gbar_0..gbar_8 in registers, phi and
-  // the gbar moments to LDS.  Rings: phi and moments of halo positions.
-  float fv[NPT][Q], gv[NPT][Q];
-#pragma unroll
-  for (int j = 0; j < NPT; ++j) {
-    const int kk = tid + j * NT;
-    const int lx0 = kk % TX, ly0 = kk / TX;
-    int mx = x0 + lx0, my = y0 + ly0;
+  // Loads of one element: own node j, phi-ring slot it, moment-ring slot it.
+  template <bool INNER>
+  __device__ __forceinline__ void issue_own(const Puller<S, INNER>& pu, int x0, int y0, int j) {
+    const int kk = threadIdx.x + j * NT;
+    int mx = x0 + kk % TX, my = y0 + kk / TX;
     if constexpr (!INNER) {
-      mx = map_axis(mx, nx, c.wall_x);
-      my = map_axis(my, ny, c.wall_y);
+      mx = map_axis(mx, pu.c.nx, pu.c.wall_x);
+      my = map_axis(my, pu.c.ny, pu.c.wall_y);
     }
-    const unsigned idx = mx + nx * my;
-    pull_all<S, INNER>(c, src, ip, mx, my, idx, fv[j], gv[j]);
-    float f0, f0l;
-    if constexpr (INNER) {
-      f0 = ip.fv(c, 0, idx);
-      f0l = ip.lo(idx);
-    } else {
-      f0 = P::f(c, src, 0, P::fofs(c, 0, idx));
-      f0l = P::f0lo(c, src, idx);
-    }
-    float sm = 0.0f;
-#pragma unroll
-    for (int i = 1; i < Q; ++i) sm += fv[j][i];
-    float hi, lo;
-    two_sum(f0, f0l + sm, hi, lo);
-    const int pk = (ly0 + R) * PW + (lx0 + R);
-    L.ph[pk] = hi;
-    L.pl[pk] = lo;
-    float m0 = 0.0f, m1x = 0.0f, m1y = 0.0f;
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      m0 += gv[j][i];
-      if (EX(i)) m1x += EX(i) > 0 ? gv[j][i] : -gv[j][i];
-      if (EY(i)) m1y += EY(i) > 0 ? gv[j][i] : -gv[j][i];
-    }
-    const int uk = (ly0 + 1) * UW + (lx0 + 1);
-    L.p[uk] = m0;
-    L.ux[uk] = m1x;
-    L.uy[uk] = m1y;
+    pu.fpop(mx, my, f0[j], lo[j], fr[j]);
+    pu.gpop(mx, my, gr[j]);
   }
-#pragma unroll
-  for (int it = 0; it < IA; ++it) {
-    const int k = tid + it * NT;
+  template <bool INNER>
+  __device__ __forceinline__ void issue_phi(const Puller<S, INNER>& pu, int x0, int y0, int it) {
+    const int k = threadIdx.x + it * NT;
     if (k < NRA) {
       int lx, ly;
       ring_pos<TX, TY, R>(k, lx, ly);
       int gx = x0 - R + lx, gy = y0 - R + ly;
       if constexpr (!INNER) {
-        gx = map_axis(gx, nx, c.wall_x);
-        gy = map_axis(gy, ny, c.wall_y);
+        gx = map_axis(gx, pu.c.nx, pu.c.wall_x);
+        gy = map_axis(gy, pu.c.ny, pu.c.wall_y);
       }
-      float hi, lo;
-      phi_pull<S, INNER>(c, src, ip, gx, gy, hi, lo);
-      L.ph[ly * PW + lx] = hi;
-      L.pl[ly * PW + lx] = lo;
+      pu.fpop(gx, gy, af0[it], alo[it], afr[it]);
     }
   }
-#pragma unroll
-  for (int it = 0; it < IC; ++it) {
-    const int k = tid + it * NT;
+  template <bool INNER>
+  __device__ __forceinline__ void issue_mom(const Puller<S, INNER>& pu, int x0, int y0, int it) {
+    const int k = threadIdx.x + it * NT;
     if (k < NRC) {
       int lx, ly;
       ring_pos<TX, TY, 1>(k, lx, ly);
       int gx = x0 - 1 + lx, gy = y0 - 1 + ly;
       if constexpr (!INNER) {
-        gx = map_axis(gx, nx, c.wall_x);
-        gy = map_axis(gy, ny, c.wall_y);
+        gx = map_axis(gx, pu.c.nx, pu.c.wall_x);
+        gy = map_axis(gy, pu.c.ny, pu.c.wall_y);
       }
-      float m0, m1x, m1y;
-      g_moments<S, INNER>(c, src, ip, gx, gy, m0, m1x, m1y);
-      L.p[ly * UW + lx] = m0;
-      L.ux[ly * UW + lx] = m1x;
-      L.uy[ly * UW + lx] = m1y;
+      pu.gpop(gx, gy, cgr[it]);
     }
   }
-  __syncthreads();
+
+  // Sums of one element into LDS; own nodes also keep their decoded
+  // populations in fv, gv.
+  __device__ __forceinline__ void consume_own(const CaseDev& c, T& L, int j, float* fv,
+                                              float* gv) const {
+    const int kk = threadIdx.x + j * NT;
+    const int lx0 = kk % TX, ly0 = kk / TX;
+    float hi, plo;
+    phi_sum<S>(c, f0[j], lo[j], fr[j], fv, hi, plo);
+    const int pk = (ly0 + R) * T::PW + (lx0 + R);
+    L.ph[pk] = hi;
+    L.pl[pk] = plo;
+    float m0, m1x, m1y;
+    g_sum<S>(c, gr[j], gv, m0, m1x, m1y);
+    const int uk = (ly0 + 1) * T::UW + (lx0 + 1);
+    L.p[uk] = m0;
+    L.ux[uk] = m1x;
+    L.uy[uk] = m1y;
+  }
+  __device__ __forceinline__ void consume_phi(const CaseDev& c, T& L, int it) const {
+    const int k = threadIdx.x + it * NT;
+    if (k < NRA) {
+      int lx, ly;
+      ring_pos<TX, TY, R>(k, lx, ly);
+      float tmp[Q], hi, plo;
+      phi_sum<S>(c, af0[it], alo[it], afr[it], tmp, hi, plo);
+      L.ph[ly * T::PW + lx] = hi;
+      L.pl[ly * T::PW + lx] = plo;
+    }
+  }
+  __device__ __forceinline__ void consume_mom(const CaseDev& c, T& L, int it) const {
+    const int k = threadIdx.x + it * NT;
+    if (k < NRC) {
+      int lx, ly;
+      ring_pos<TX, TY, 1>(k, lx, ly);
+      float tmp[Q], m0, m1x, m1y;
+      g_sum<S>(c, cgr[it], tmp, m0, m1x, m1y);
+      L.p[ly * T::UW + lx] = m0;
+      L.ux[ly * T::UW + lx] = m1x;
+      L.uy[ly * T::UW + lx] = m1y;
+    }
+  }
+
+  // Each element loaded and summed in turn (the compiler hoists loads as
+  // far as registers allow).
+  template <bool INNER>
+  __device__ __forceinline__ void load_all(const CaseDev& c, const char* src, int x0, int y0,
+                                           T& L, float (*fv)[Q], float (*gv)[Q]) {
+    const Puller<S, INNER> pu(c, src);
+#pragma unroll
+    for (int j = 0; j < NPT; ++j) {
+      issue_own<INNER>(pu, x0, y0, j);
+      consume_own(c, L, j, fv[j], gv[j]);
+    }
+#pragma unroll
+    for (int it = 0; it < IA; ++it) {
+      issue_phi<INNER>(pu, x0, y0, it);
+      consume_phi(c, L, it);
+    }
+#pragma unroll
+    for (int it = 0; it < IC; ++it) {
+      issue_mom<INNER>(pu, x0, y0, it);
+      consume_mom(c, L, it);
+    }
+  }
+};
+
+// Phases B, C and D of one tile whose phi and gbar moments are in LDS (and
+// a barrier has passed since they were written); fv, gv hold the own nodes'
+// pulled populations.  Ends with a barrier, after which LDS is free.
+// INNER: every pulled population of the phi region lies inside the grid (no
+// wrap, no wall), so no position needs mirroring.
+template <int TX, int TY, int NPT, int RF, int S, bool FIELDS, bool INNER>
+__device__ __forceinline__ void tile_bcd(TileLds<TX, TY, RF>& L, const CaseDev& c, int x0, int y0,
+                                         char* dst, const FieldOut& fo, const float (*fv)[Q],
+                                         const float (*gv)[Q]) {
+  using T = TileLds<TX, TY, RF>;
+  constexpr int NT = TX * TY / NPT;
+  constexpr int R = T::R, RM = T::RM;
+  constexpr int PW = T::PW, MW = T::MW, MH = T::MH, UW = T::UW, UH = T::UH;
+  constexpr int IB = (MW * MH + NT - 1) / NT;
+  constexpr int ICC = (UW * UH + NT - 1) / NT;
+  const FF<PW> phi{L.ph, L.pl};
+  const int tid = threadIdx.x;
+  const int nx = c.nx, ny = c.ny;
+  const OutPtrs<S, Q> op(c, dst);
 
   // ---- B: mu over the tile + RM
 #pragma unroll
@@ -385,7 +430,8 @@ __device__ __forceinline__ void tile_body(TileLds<TX, TY, RF>& L, const CaseDev&
   for (int it = 0; it < ICC; ++it) {
     const int k = tid + it * NT;
     if (k < UW * UH) {
-      int lx = k % UW, ly = k / UW;
+      const int kx = k % UW, ky = k / UW;
+      int lx = kx, ly = ky;
       if constexpr (!INNER) {
         lx = mirror_local(lx, x0 - 1, nx, c.wall_x, UW);
         ly = mirror_local(ly, y0 - 1, ny, c.wall_y, UH);
@@ -402,6 +448,14 @@ __device__ __forceinline__ void tile_body(TileLds<TX, TY, RF>& L, const CaseDev&
       L.ux[k] = ux;
       L.uy[k] = uy;
       L.p[k] = p;
+      // tile nodes keep grad phi and lap mu for D (no mirroring applies to
+      // a node inside the grid, and ragged positions outside it are unused)
+      const int tx = kx - 1, ty = ky - 1;
+      if (tx >= 0 && tx < TX && ty >= 0 && ty < TY) {
+        L.gx[ty * TX + tx] = gx;
+        L.gy[ty * TX + tx] = gy;
+        L.lm[ty * TX + tx] = lmu;
+      }
     }
   }
   __syncthreads();
@@ -419,10 +473,9 @@ __device__ __forceinline__ void tile_body(TileLds<TX, TY, RF>& L, const CaseDev&
     const int uc = (ly0 + 1) * UW + (lx0 + 1);
     const float phh = L.ph[pc], phl = L.pl[pc];
     const float ph = phh + phl;
-    float gx, gy;
-    grad_ff<PW>(phi, pc, gx, gy);
+    const float gx = L.gx[kk], gy = L.gy[kk];
     const float mu = L.mu[my * MW + mx];
-    const float lmu = RF ? lap_only<MW>(L.mu, mx, my) : 0.0f;
+    const float lmu = L.lm[kk];
     const float ux = L.ux[uc];
     const float uy = L.uy[uc];
     const float p = L.p[uc];
@@ -496,32 +549,53 @@ __device__ __forceinline__ void tile_body(TileLds<TX, TY, RF>& L, const CaseDev&
 // RF = 1: lap mu is formed (corrected model, or the F_a dump); phi halo 3.
 // WPE > 0 asks the compiler for at least that many waves per SIMD (fewer
 // registers, more tiles in flight per CU).
+//
+// Tile order: workgroup b runs on XCD b % 8.  Each XCD walks its own
+// contiguous chunk of the tile list (which the host orders in narrow
+// vertical strips), so the tiles in flight on one XCD are neighbours and
+// share their halos through that XCD's L2.
+struct TileWalk {
+  int t, t_end, step;
+  __device__ __forceinline__ explicit TileWalk(int ntiles) {
+    step = gridDim.x >> 3;
+    const int xcd = blockIdx.x & 7;
+    const int chunk = (ntiles + 7) >> 3;
+    t_end = min(ntiles, (xcd + 1) * chunk);
+    t = xcd * chunk + (blockIdx.x >> 3);
+  }
+};
+
+template <int TX, int TY, int RF>
+__device__ __forceinline__ bool tile_inner(const CaseDev& c, const TileDev& tl) {
+  constexpr int R = TileLds<TX, TY, RF>::R;
+  return (tl.x0 - R - 1 >= 0) && (tl.x0 + TX + R + 1 <= c.nx) && (tl.y0 - R - 1 >= 0) &&
+         (tl.y0 + TY + R + 1 <= c.ny);
+}
+
+// One tile per iteration: all loads of a tile are issued in one batch,
+// summed into LDS, then B, C, D.
 template <int TX, int TY, int NPT, int RF, int S, bool FIELDS, int WPE>
 __global__ void __launch_bounds__(TX * TY / NPT)
 __attribute__((amdgpu_waves_per_eu(WPE > 0 ? WPE : 1)))
 k_tile(const CaseDev* __restrict__ cases, const TileDev* __restrict__ tiles, int ntiles,
        int parity, FieldOut fo) {
-  constexpr int R = TileLds<TX, TY, RF>::R;
   __shared__ TileLds<TX, TY, RF> lds;
-  // XCD-aware order: workgroup b runs on XCD b % 8.  Each XCD walks its own
-  // contiguous chunk of the tile list (which the host orders in narrow
-  // vertical strips), so the tiles in flight on one XCD are neighbours and
-  // share their halos through that XCD's L2.
-  const int per_xcd = gridDim.x >> 3;
-  const int xcd = blockIdx.x & 7;
-  const int chunk = (ntiles + 7) >> 3;
-  const int t_end = min(ntiles, (xcd + 1) * chunk);
-  for (int t = xcd * chunk + (blockIdx.x >> 3); t < t_end; t += per_xcd) {
-    const TileDev tl = tiles[t];
+  for (TileWalk w(ntiles); w.t < w.t_end; w.t += w.step) {
+    const TileDev tl = tiles[w.t];
     const CaseDev c = cases[tl.icase];
     const char* src = parity ? c.state[1] : c.state[0];
     char* dst = parity ? c.state[0] : c.state[1];
-    const bool inner = (tl.x0 - R - 1 >= 0) && (tl.x0 + TX + R + 1 <= c.nx) &&
-                       (tl.y0 - R - 1 >= 0) && (tl.y0 + TY + R + 1 <= c.ny);
-    if (inner)
-      tile_body<TX, TY, NPT, RF, S, FIELDS, true>(lds, c, tl.x0, tl.y0, src, dst, fo);
-    else
-      tile_body<TX, TY, NPT, RF, S, FIELDS, false>(lds, c, tl.x0, tl.y0, src, dst, fo);
+    TileLoads<TX, TY, NPT, RF, S> ld;
+    float fv[NPT][Q], gv[NPT][Q];
+    if (tile_inner<TX, TY, RF>(c, tl)) {
+      ld.template load_all<true>(c, src, tl.x0, tl.y0, lds, fv, gv);
+      __syncthreads();
+      tile_bcd<TX, TY, NPT, RF, S, FIELDS, true>(lds, c, tl.x0, tl.y0, dst, fo, fv, gv);
+    } else {
+      ld.template load_all<false>(c, src, tl.x0, tl.y0, lds, fv, gv);
+      __syncthreads();
+      tile_bcd<TX, TY, NPT, RF, S, FIELDS, false>(lds, c, tl.x0, tl.y0, dst, fo, fv, gv);
+    }
   }
 }
 
@@ -625,7 +699,7 @@ hipError_t launch_step_v(const LaunchArgs& a) {
 const TileShape kD2Q9Tiles[] = {{32, 16, 1, 512}, {64, 8, 1, 512},  {64, 16, 1, 1024},
                                 {32, 8, 1, 256},  {128, 4, 1, 512}, {64, 8, 1, 512},
                                 {64, 16, 1, 512}, {32, 16, 1, 256}, {64, 8, 1, 256},
-                                {128, 8, 1, 512}};
+                                {32, 32, 1, 512}};
 const int kD2Q9TileCount = sizeof(kD2Q9Tiles) / sizeof(kD2Q9Tiles[0]);
 
 hipError_t d2q9_step(int variant, const LaunchArgs& a) {
@@ -636,10 +710,10 @@ hipError_t d2q9_step(int variant, const LaunchArgs& a) {
     case 3: return launch_step_v<32, 8>(a);
     case 4: return launch_step_v<128, 4>(a);
     case 5: return launch_step_v<64, 8, 1, 6>(a);
-    case 6: return launch_step_v<64, 16, 2>(a);
-    case 7: return launch_step_v<32, 16, 2>(a);
-    case 8: return launch_step_v<64, 8, 2>(a);
-    case 9: return launch_step_v<128, 8, 2>(a);
+    case 6: return launch_step_v<64, 16, 2, 4>(a);
+    case 7: return launch_step_v<32, 16, 2, 4>(a);
+    case 8: return launch_step_v<64, 8, 2, 4>(a);
+    case 9: return launch_step_v<32, 32, 2, 4>(a);
     default: return hipErrorInvalidValue;
   }
 }

@@ -7,6 +7,8 @@
 #include <hip/hip_fp16.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace lbm {
 
 enum Storage { ST_FP32 = 0, ST_FP16 = 1, ST_BF16 = 2 };
@@ -119,6 +121,20 @@ struct Pops {
     if constexpr (S == ST_FP32) return ((unsigned)(Q + i) * c.stride + j) * 4u;
     else return 4u * c.stride + ((unsigned)(Q - 1 + i) * c.stride + j) * 2u;
   }
+  // Stored word of f_i (i > 0) and g_i -> value
+  static __device__ __forceinline__ float dec_f(const CaseDev& c, float w) { return w; }
+  static __device__ __forceinline__ float dec_f(const CaseDev& c, uint16_t w) {
+    return dec16<S>(w) * c.inv_scale_f;
+  }
+  static __device__ __forceinline__ float dec_g(const CaseDev& c, float w, float wi) { return w; }
+  static __device__ __forceinline__ float dec_g(const CaseDev& c, uint16_t w, float wi) {
+    return dec16<S>(w) * c.inv_scale_g + wi * c.p0;
+  }
+  // low part of f_0 from its stored BF16 word (FP32 storage only; zero otherwise)
+  static __device__ __forceinline__ float dec_lo(uint16_t w) {
+    if constexpr (S == ST_FP32) return dec_bf16(w);
+    else return 0.0f;
+  }
   // f_i at a byte offset (i only selects the width: f_0 is always a float)
   static __device__ __forceinline__ float f(const CaseDev& c, const char* base, int i,
                                             unsigned ofs) {
@@ -126,22 +142,18 @@ struct Pops {
       return gload<float>(base, ofs);
     } else {
       if (i == 0) return gload<float>(base, ofs);
-      return dec16<S>(gload<uint16_t>(base, ofs)) * c.inv_scale_f;
+      return dec_f(c, gload<uint16_t>(base, ofs));
     }
   }
   static __device__ __forceinline__ float g(const CaseDev& c, const char* base, unsigned ofs,
                                             float wi) {
-    if constexpr (S == ST_FP32) {
-      (void)wi;
-      return gload<float>(base, ofs);
-    } else {
-      return dec16<S>(gload<uint16_t>(base, ofs)) * c.inv_scale_g + wi * c.p0;
-    }
+    if constexpr (S == ST_FP32) return gload<float>(base, ofs);
+    else return dec_g(c, gload<uint16_t>(base, ofs), wi);
   }
   // low part of f_0 (FP32 storage only; zero otherwise)
   static __device__ __forceinline__ float f0lo(const CaseDev& c, const char* base, unsigned j) {
     if constexpr (S == ST_FP32) {
-      return dec_bf16(gload<uint16_t>(base, (unsigned)(2 * Q) * 4u * c.stride + 2u * j));
+      return dec_lo(gload<uint16_t>(base, (unsigned)(2 * Q) * 4u * c.stride + 2u * j));
     } else {
       return 0.0f;
     }
@@ -155,7 +167,7 @@ struct Pops {
     } else {
       const uint16_t h = enc16<S>(v * c.scale_f);
       gstore<uint16_t>(base, fofs(c, i, j), h);
-      return dec16<S>(h) * c.inv_scale_f;
+      return Pops<S, Q>::dec_f(c, h);
     }
   }
   // f_0 = hi + lo; the 16-bit layouts keep hi + lo rounded to one float
@@ -206,7 +218,7 @@ struct OutPtrs {
     } else {
       const uint16_t h = enc16<S>(v * c.scale_f);
       gstore<uint16_t>(f[i], 2u * idx, h);
-      return dec16<S>(h) * c.inv_scale_f;
+      return Pops<S, Q>::dec_f(c, h);
     }
   }
   __device__ __forceinline__ void put_g(const CaseDev& c, int i, unsigned idx, float v,

@@ -134,17 +134,22 @@ def test_ragged_walls_parity(torch, hip, shape, wall, rf):
     phi, u, p = W.droplet_fields(prm, centre, radius, impact_u=0.02, noise=noise)
     case = W.Case(prm, phi, u, p)
     for variant in range(len(hip.variants())):
-        sim = run_gpu(hip, case, 300, variant=variant)
-        got = sim.moments()
-        if variant == 0:
-            want = run_oracle(case, 300).fields()
-            dphi, du, dp = errors(got, want)
-            print(f"{shape} {wall} rf={rf}: max|dphi|={dphi:.2e} relL2(u)={du:.2e}")
-            assert dphi <= PHI_TOL and du <= U_TOL
-            first = sim.get_state()
-        else:
-            # every tile shape computes each node with the same arithmetic
-            assert np.array_equal(sim.get_state(), first), f"variant {variant} differs"
+        # grid 8: one workgroup per XCD walks many tiles (the persistent
+        # path, with interior and boundary tiles in one walk)
+        for grid in (0, 8):
+            sim = run_gpu(hip, case, 300, variant=variant, grid=grid)
+            got = sim.moments()
+            if variant == 0 and grid == 0:
+                want = run_oracle(case, 300).fields()
+                dphi, du, dp = errors(got, want)
+                print(f"{shape} {wall} rf={rf}: max|dphi|={dphi:.2e} relL2(u)={du:.2e}")
+                assert dphi <= PHI_TOL and du <= U_TOL
+                first = sim.get_state()
+            else:
+                # every tile shape computes each node with the same arithmetic
+                assert np.array_equal(sim.get_state(), first), \
+                    f"variant {variant} grid {grid} differs"
+            sim.close()
 
 
 def test_fields_mu_and_fa_match_oracle(torch, hip):
@@ -176,9 +181,13 @@ def test_batched_equals_single(torch, hip):
              for k, n in enumerate((64, 96, 128, 40))]
     cases[3].params["wall"] = [1, 1, 0]
     batch = run_gpu(hip, cases, 60)
+    # a persistent launch whose workgroups walk tiles of several cases, with
+    # two nodes per thread
+    walked = run_gpu(hip, cases, 60, variant=6, grid=16)
     for k, c in enumerate(cases):
         single = run_gpu(hip, c, 60)
         assert np.array_equal(batch.get_state(k), single.get_state(0)), k
+        assert np.array_equal(walked.get_state(k), single.get_state(0)), k
 
 
 # --------------------------------------------------------------- diagnostics

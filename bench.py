@@ -135,6 +135,29 @@ def leg_ensemble(torch, W, hip, storage, steps=200, warmup=20):
     return out
 
 
+def pull_copy_ceiling(torch, hip, lattice, storage, dims, reps=200):
+    """Seconds per launch of the pull-copy calibration kernel: the step's
+    reads (every population from x - e_i) and writes in the same plane
+    layout, without arithmetic.  The practical ceiling of the step's memory
+    access pattern on this device."""
+    nb = hip.pull_copy_bytes(lattice, storage, dims)
+    a = torch.zeros(nb, dtype=torch.uint8, device="cuda")
+    b = torch.zeros(nb, dtype=torch.uint8, device="cuda")
+    for k in range(10):
+        hip.pull_copy_bw(lattice, storage, dims, a if k % 2 == 0 else b, b if k % 2 == 0 else a)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for k in range(reps):
+        hip.pull_copy_bw(lattice, storage, dims, a if k % 2 == 0 else b, b if k % 2 == 0 else a)
+    e1.record()
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) / 1e3 / reps
+    del a, b
+    return t
+
+
 def cpu_baseline(W, seconds):
     """The FP64 oracle as it stands on the host cores, on the same workload,
     stepping until about `seconds` have passed."""
@@ -199,7 +222,10 @@ def main():
     bpl = BYTES_PER_LU[a.storage]
     achieved = main_leg["nodes"] * bpl / (main_leg["seconds"] / a.steps) / 1e9
     key = f"{a.workload}_{a.storage}_rf{a.remove_fa}_v{main_leg['variant']}"
-    traffic, traffic_bytes = traffic_for(key, main_leg["seconds"] / a.steps)
+    step_s = main_leg["seconds"] / a.steps
+    traffic, traffic_bytes = traffic_for(key, step_s)
+    dims = (1024, 512) if a.workload == "splash1024x512" else (4096, 4096)
+    pc_s = pull_copy_ceiling(torch, hip, hip.D2Q9, a.storage, dims)
     out = {
         "metric": "lattice updates/s (MLUPS), fused D2Q9 phase-field step",
         "value": round(main_leg["mlups"], 1),
@@ -223,7 +249,10 @@ def main():
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "traffic_bytes_per_launch": traffic_bytes,
                      "bytes_per_lu": bpl, "kernel": "k_tile (fused D2Q9 step)",
-                     "variant": main_leg["variant"]},
+                     "variant": main_leg["variant"],
+                     # the same reads and writes without arithmetic (lbm_pull_copy_bw)
+                     "pull_copy_us": round(pc_s * 1e6, 2),
+                     "frac_of_pull_copy": round(pc_s / step_s, 4)},
         "check": {"mass_drift_rel": main_leg["mass_drift_rel"],
                   "nonfinite": main_leg["nonfinite"], "umax": main_leg["umax"]},
     }

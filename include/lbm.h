@@ -190,6 +190,18 @@ int lbm_encode16(int32_t storage, const float* in, uint16_t* out, int64_t n,
  * pattern (achievable-bandwidth calibration). */
 int lbm_copy_bw(const float* in, float* out, int64_t n, void* hip_stream);
 
+/* Pull-copy calibration: the memory traffic of one step of an nx x ny x nz
+ * grid without its arithmetic.  src and dst each hold one copy of the stored
+ * populations in the step's plane layout with a plane stride of nx*ny*nz
+ * elements (storage LBM_FP32: 2q float planes then one BF16 plane,
+ * (8q + 2) bytes per node; LBM_FP16/LBM_BF16: one float plane then 2q - 1
+ * 16-bit planes, (4q + 2) bytes per node).  Every word of node x is read from
+ * x - e_i (from x itself where that leaves the grid) and written to x.  The
+ * output has no meaning beyond the timing.  Device pointers, caller-owned;
+ * enqueued on hip_stream.  LBM_ERR_ARG on bad sizes or null buffers. */
+int lbm_pull_copy_bw(int32_t lattice, int32_t storage, int32_t nx, int32_t ny, int32_t nz,
+                     const void* src, void* dst, void* hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -97,6 +97,8 @@ def lib():
                                    _vp]
     L.lbm_encode16.argtypes = [C.c_int32, _vp, _vp, C.c_int64, _vp]
     L.lbm_copy_bw.argtypes = [_vp, _vp, C.c_int64, _vp]
+    L.lbm_pull_copy_bw.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, _vp,
+                                   _vp, _vp]
     _lib = L
     return L
 
@@ -309,6 +311,24 @@ def encode16(storage, x):
                               C.c_void_p(x.data_ptr()), C.c_void_p(out.data_ptr()), x.numel(),
                               _stream_handle(torch, x.device)))
     return out
+
+
+def pull_copy_bytes(lattice, storage, dims):
+    """Bytes of one state copy with plane stride nx*ny*nz (see lbm_pull_copy_bw)."""
+    q = 9 if lattice == D2Q9 else 19
+    n = int(np.prod(dims))
+    st = STORAGE[storage] if isinstance(storage, str) else storage
+    return n * (8 * q + 2 if st == STORAGE["fp32"] else 4 * q + 2)
+
+
+def pull_copy_bw(lattice, storage, dims, src, dst):
+    """The step's pull traffic without arithmetic, src -> dst (uint8 device
+    tensors of pull_copy_bytes bytes)."""
+    import torch
+    st = STORAGE[storage] if isinstance(storage, str) else storage
+    nz = dims[2] if len(dims) > 2 else 1
+    _check(lib().lbm_pull_copy_bw(lattice, st, dims[0], dims[1], nz, C.c_void_p(src.data_ptr()),
+                                  C.c_void_p(dst.data_ptr()), _stream_handle(torch, src.device)))
 
 
 def copy_bw(x, y):

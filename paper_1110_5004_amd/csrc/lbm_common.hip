@@ -87,6 +87,64 @@ hipError_t copy_bw(const float* in, float* out, long long n, hipStream_t stream)
   return hipGetLastError();
 }
 
+// Pull-copy: the data movement of one step without its arithmetic.  Every
+// stored word of node idx is read from the node the step pulls it from
+// (x - e_i, or idx itself where that leaves the grid) and written to idx.
+template <int LAT, int S>
+__global__ void __launch_bounds__(256)
+k_pull_copy(CaseDev c, const char* __restrict__ src, char* __restrict__ dst) {
+  constexpr int Q = LAT == 0 ? d2q9::Q : d3q19::Q;
+  using P = Pops<S, Q>;
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= c.n) return;
+  const int x = idx % c.nx;
+  const int y = (idx / c.nx) % c.ny;
+  const int z = idx / (c.nx * c.ny);
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    int ex, ey, ez;
+    if constexpr (LAT == 0) {
+      ex = d2q9::EX(i); ey = d2q9::EY(i); ez = 0;
+    } else {
+      ex = d3q19::EX(i); ey = d3q19::EY(i); ez = d3q19::EZ(i);
+    }
+    const bool in = x - ex >= 0 && x - ex < c.nx && y - ey >= 0 && y - ey < c.ny &&
+                    z - ez >= 0 && z - ez < c.nz;
+    const unsigned j = in ? (unsigned)(idx - ex - c.nx * (ey + c.ny * ez)) : (unsigned)idx;
+    if (S == ST_FP32 || i == 0)
+      gstore<uint32_t>(dst, P::fofs(c, i, idx), gload<uint32_t>(src, P::fofs(c, i, j)));
+    else
+      gstore<uint16_t>(dst, P::fofs(c, i, idx), gload<uint16_t>(src, P::fofs(c, i, j)));
+    if (S == ST_FP32)
+      gstore<uint32_t>(dst, P::gofs(c, i, idx), gload<uint32_t>(src, P::gofs(c, i, j)));
+    else
+      gstore<uint16_t>(dst, P::gofs(c, i, idx), gload<uint16_t>(src, P::gofs(c, i, j)));
+  }
+  if (S == ST_FP32) {
+    const unsigned lo = (unsigned)(2 * Q) * 4u * c.stride;
+    gstore<uint16_t>(dst, lo + 2u * idx, gload<uint16_t>(src, lo + 2u * idx));
+  }
+}
+
+hipError_t pull_copy(int lattice, int storage, const CaseDev& c, const void* src, void* dst,
+                     hipStream_t stream) {
+  const int grid = (c.n + 255) / 256;
+  const char* s = static_cast<const char*>(src);
+  char* d = static_cast<char*>(dst);
+  if (lattice == 0) {
+    if (storage == ST_FP32)
+      hipLaunchKernelGGL((k_pull_copy<0, ST_FP32>), dim3(grid), dim3(256), 0, stream, c, s, d);
+    else
+      hipLaunchKernelGGL((k_pull_copy<0, ST_FP16>), dim3(grid), dim3(256), 0, stream, c, s, d);
+  } else {
+    if (storage == ST_FP32)
+      hipLaunchKernelGGL((k_pull_copy<1, ST_FP32>), dim3(grid), dim3(256), 0, stream, c, s, d);
+    else
+      hipLaunchKernelGGL((k_pull_copy<1, ST_FP16>), dim3(grid), dim3(256), 0, stream, c, s, d);
+  }
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- FP64 reductions
 // Sums (and one max) over the nodes of one case, from the dumped fields.
 // Every node goes to a fixed thread of a fixed workgroup; threads combine by

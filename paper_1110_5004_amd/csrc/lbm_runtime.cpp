@@ -745,4 +745,27 @@ int lbm_copy_bw(const float* in, float* out, int64_t n, void* hip_stream) {
   return LBM_OK;
 }
 
+int lbm_pull_copy_bw(int32_t lattice, int32_t storage, int32_t nx, int32_t ny, int32_t nz,
+                     const void* src, void* dst, void* hip_stream) {
+  if (lattice != LBM_D2Q9 && lattice != LBM_D3Q19) return fail(LBM_ERR_ARG, "bad lattice");
+  if (storage != LBM_FP32 && storage != LBM_FP16 && storage != LBM_BF16)
+    return fail(LBM_ERR_ARG, "bad storage");
+  if (lattice == LBM_D2Q9) nz = 1;
+  if (nx < 1 || ny < 1 || nz < 1) return fail(LBM_ERR_ARG, "bad grid");
+  const long long n = (long long)nx * ny * nz;
+  const int q = lattice == LBM_D2Q9 ? 9 : 19;
+  if ((double)lbm::copy_bytes(storage, q, n) >= 4294967296.0)
+    return fail(LBM_ERR_ARG, "one copy must stay below 4 GiB");
+  if (!src || !dst) return fail(LBM_ERR_ARG, "bad buffers");
+  CaseDev c{};
+  c.nx = nx;
+  c.ny = ny;
+  c.nz = nz;
+  c.n = (int)n;
+  c.stride = (unsigned)n;
+  HIPCHK(lbm::pull_copy(lattice == LBM_D2Q9 ? 0 : 1, storage == LBM_FP32 ? lbm::ST_FP32 : lbm::ST_FP16,
+                        c, src, dst, reinterpret_cast<hipStream_t>(hip_stream)));
+  return LBM_OK;
+}
+
 }  // extern "C"

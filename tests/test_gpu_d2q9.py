@@ -251,3 +251,44 @@ def test_splash1024x512_early_window(torch, hip):
         print(f"splash rf={rf} 2000 steps: mass drift {d['mass_drift_rel']:.2e} "
               f"umax {d['umax']:.4f}")
         assert d["nonfinite"] == 0 and d["mass_drift_rel"] <= 1e-6
+
+
+# ------------------------------------------------------- pull-copy calibration
+@pytest.mark.parametrize("lattice,dims,storage", [(0, (37, 23, 1), "fp32"),
+                                                  (0, (40, 17, 1), "fp16"),
+                                                  (1, (11, 9, 7), "fp32"),
+                                                  (1, (8, 13, 6), "bf16")])
+def test_pull_copy_moves_words(torch, hip, lattice, dims, storage):
+    """Every stored word of node x comes from x - e_i (x itself where that
+    leaves the grid), plane by plane; checked against a numpy shift."""
+    nb = hip.pull_copy_bytes(lattice, storage, dims)
+    rng = np.random.default_rng(nb)
+    src_h = rng.integers(0, 256, nb, dtype=np.uint8)
+    src = torch.from_numpy(src_h).cuda()
+    dst = torch.zeros(nb, dtype=torch.uint8, device="cuda")
+    hip.pull_copy_bw(lattice, storage, dims, src, dst)
+    got = dst.cpu().numpy()
+    nx, ny, nz = dims
+    n = nx * ny * nz
+    e = O.lattice(lattice)[0]
+    q = len(e)
+    # plane list: (byte offset, word size)
+    if storage == "fp32":
+        planes = [(k * 4 * n, 4) for k in range(2 * q)]
+        tail = [(2 * q * 4 * n, 2)]
+    else:
+        planes = [(0, 4)] + [(4 * n + k * 2 * n, 2) for k in range(2 * q - 1)]
+        tail = []
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    x, y, z = x.ravel(), y.ravel(), z.ravel()
+    want = np.zeros_like(src_h)
+    for k, (off, w) in enumerate(planes):
+        ex, ey, ez = e[k % q]
+        inside = ((x - ex >= 0) & (x - ex < nx) & (y - ey >= 0) & (y - ey < ny) &
+                  (z - ez >= 0) & (z - ez < nz))
+        j = np.where(inside, np.arange(n) - ex - nx * (ey + ny * ez), np.arange(n))
+        words_src = src_h[off:off + w * n].reshape(n, w)
+        want[off:off + w * n] = words_src[j].ravel()
+    for off, w in tail:
+        want[off:off + w * n] = src_h[off:off + w * n]
+    assert np.array_equal(got, want)

@@ -93,8 +93,13 @@ def leg(torch, W, hip, storage, remove_fa, steps, warmup, workload="splash1024x5
 
 def leg_3d(torch, W, hip, storage, remove_fa, steps=100, warmup=10):
     """D3Q19 splash 256x256x128 (periodic x, y, walls z)."""
+    from paper_1110_5004_amd import tune
     case = W.splash_3d(remove_fa=remove_fa)
+    probe = hip.Simulation([case], storage=storage)
+    rec = tune.tune(probe, steps=10)
+    probe.close()
     sim = hip.Simulation([case], storage=storage)
+    sim.set_launch(rec["variant"], rec["grid"], rec["graph_steps"])
     t = time_gpu(torch, sim, steps, warmup)
     d = sim.diagnostics()
     sim.close()

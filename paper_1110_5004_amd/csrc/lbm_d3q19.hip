@@ -2,11 +2,11 @@
 //
 // The same model as the D2Q9 step (Eq. 1a, Eq. 4a, Eq. 8, the -F_a switch of
 // the paragraph after Eq. 12, isotropic central stencils), on 19 velocities.
-// A step is four node-parallel kernels that pass fields through HBM:
-//   k3_pull     pull f and gbar; phi (float-float) and the gbar moments
-//   k3_mu       mu = theta'(phi) - kappa lap phi
-//   k3_fields   grad phi, lap mu, u and p (with -F_a in the corrected model)
-//   k3_collide  grad p -> grad psi, BGK collision of f and gbar, store
+// A step is three kernels that pass fields through HBM:
+//   k3_pull      pull f and gbar; phi (float-float) and the gbar moments
+//   k3_fields_t  on LDS tiles: mu = theta'(phi) - kappa lap phi, then grad
+//                phi, lap mu, u and p (with -F_a in the corrected model)
+//   k3_collide   grad p -> grad psi, BGK collision of f and gbar, store
 // Stencil neighbours come from the field planes through the periodic / mirror
 // mapping, so positions beyond a wall read their mirror node.
 #include "lbm_dev.h"
@@ -96,46 +96,8 @@ __global__ void __launch_bounds__(256) k3_pull(CaseDev c, int parity, Fields3 fl
   fl.m1z[idx] = mz;
 }
 
-// Isotropic Laplacian 6 sum_i w_i (phi_i - phi) and gradient 3 sum_i w_i e_i
-// phi_i of a float-float field (differences of close values are exact).
-__device__ __forceinline__ void grad_lap_ff(const CaseDev& c, const float* h, const float* l,
-                                            int x, int y, int z, unsigned idx, bool in,
-                                            float* g, float* lap) {
-  const float h0 = h[idx], l0 = l[idx];
-  float ax = 0.0f, ay = 0.0f, az = 0.0f, la = 0.0f, le = 0.0f;
-#pragma unroll
-  for (int i = 1; i < Q; ++i) {
-    const unsigned j = nbr(c, x, y, z, i, in, idx);
-    const float d = (h[j] - h0) + (l[j] - l0);   // phi_i - phi
-    if (i <= 6) la += d;
-    else le += d;
-    // gradient from differences: sum w_i e_i (phi_i - phi) = sum w_i e_i phi_i
-    const float w = i <= 6 ? (1.0f / 6.0f) : (1.0f / 12.0f);  // 3 w_i
-    if (EX(i)) ax += EX(i) > 0 ? w * d : -w * d;
-    if (EY(i)) ay += EY(i) > 0 ? w * d : -w * d;
-    if (EZ(i)) az += EZ(i) > 0 ? w * d : -w * d;
-  }
-  if (g) {
-    g[0] = ax;
-    g[1] = ay;
-    g[2] = az;
-  }
-  if (lap) *lap = (1.0f / 3.0f) * la + (1.0f / 6.0f) * le;
-}
-
-__device__ __forceinline__ float lap_f(const CaseDev& c, const float* f, int x, int y, int z,
-                                       unsigned idx, bool in) {
-  const float f0 = f[idx];
-  float la = 0.0f, le = 0.0f;
-#pragma unroll
-  for (int i = 1; i < Q; ++i) {
-    const float d = f[nbr(c, x, y, z, i, in, idx)] - f0;
-    if (i <= 6) la += d;
-    else le += d;
-  }
-  return (1.0f / 3.0f) * la + (1.0f / 6.0f) * le;
-}
-
+// Isotropic gradient 3 sum_i w_i e_i f_i of a node field, from differences
+// to the centre (the stencil of the step's grad p).
 __device__ __forceinline__ void grad_f(const CaseDev& c, const float* f, int x, int y, int z,
                                        unsigned idx, bool in, float* g) {
   const float f0 = f[idx];
@@ -153,44 +115,149 @@ __device__ __forceinline__ void grad_f(const CaseDev& c, const float* f, int x, 
   g[2] = az;
 }
 
-// ---- 2: chemical potential
-__global__ void __launch_bounds__(256) k3_mu(CaseDev c, Fields3 fl) {
-  const unsigned idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (unsigned)c.n) return;
-  int x, y, z;
-  coords(c, idx, x, y, z);
-  const bool in = is_interior(c, x, y, z);
-  float lap;
-  grad_lap_ff(c, fl.phh, fl.phl, x, y, z, idx, in, nullptr, &lap);
-  fl.mu[idx] = dtheta(c, fl.phh[idx], fl.phl[idx]) - c.kappa * lap;
+// ---- 2+3: mu, grad phi, lap mu, u, p on a TX x TY x TZ tile through LDS.
+// phi (float-float) is staged over the tile + 2, mu is formed over the tile
+// + 1, then each node of the tile forms its gradient, lap mu, u and p.  A
+// staged position holds the value of the node it maps to (periodic wrap or
+// mirror ghost); a mu position beyond a wall is computed around its mirror
+// position, so that it equals the mirror node's mu as the step defines it.
+// Stencil sums run over i = 1..18 in lattice order, as in the node-parallel
+// definition, so the result does not depend on the tile shape.
+template <int TX, int TY, int TZ>
+struct FieldTile {
+  static constexpr int NT = TX * TY * TZ;
+  static constexpr int PX = TX + 4, PY = TY + 4, PZ = TZ + 4;  // phi region
+  static constexpr int MX = TX + 2, MY = TY + 2, MZ = TZ + 2;  // mu region
+  static constexpr int NP = PX * PY * PZ, NM = MX * MY * MZ;
+  float ph[NP];
+  float pl[NP];
+  float mu[NM];
+};
+
+// Offset of neighbour e_i in a region of row pitch X and plane pitch X * Y.
+template <int X, int Y>
+__device__ __forceinline__ constexpr int nofs(int i) {
+  return EX(i) + X * (EY(i) + Y * EZ(i));
 }
 
-// ---- 3: grad phi, lap mu, u, p.  want_lmu forms lap mu also for the
-// original model (field dump of F_a).
-__global__ void __launch_bounds__(256) k3_fields(CaseDev c, Fields3 fl, int want_lmu) {
-  const unsigned idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (unsigned)c.n) return;
-  int x, y, z;
-  coords(c, idx, x, y, z);
-  const bool in = is_interior(c, x, y, z);
-  float g[3];
-  grad_lap_ff(c, fl.phh, fl.phl, x, y, z, idx, in, g, nullptr);
-  const float lmu = (want_lmu || c.corr != 0.0f) ? lap_f(c, fl.mu, x, y, z, idx, in) : 0.0f;
-  const float ph = fl.phh[idx] + fl.phl[idx];
-  const float mu = fl.mu[idx];
+template <int TX, int TY, int TZ>
+__global__ void __launch_bounds__(TX * TY * TZ)
+k3_fields_t(CaseDev c, Fields3 fl, int want_lmu) {
+  using T = FieldTile<TX, TY, TZ>;
+  constexpr int PX = T::PX, PY = T::PY, MX = T::MX, MY = T::MY;
+  __shared__ T L;
+  // XCD-aware tile order: workgroup b runs on XCD b % 8 and takes the b / 8-th
+  // tile of that XCD's contiguous chunk (neighbouring tiles share L2).
+  const int ntx = (c.nx + TX - 1) / TX, nty = (c.ny + TY - 1) / TY, ntz = (c.nz + TZ - 1) / TZ;
+  const int ntiles = ntx * nty * ntz;
+  const int chunk = (ntiles + 7) >> 3;
+  const int t = (blockIdx.x & 7) * chunk + (blockIdx.x >> 3);
+  if (blockIdx.x >= (unsigned)(8 * chunk) || t >= ntiles) return;
+  const int x0 = (t % ntx) * TX, y0 = ((t / ntx) % nty) * TY, z0 = (t / (ntx * nty)) * TZ;
+  const int tid = threadIdx.x;
+  const bool inner = x0 >= 2 && x0 + TX + 2 <= c.nx && y0 >= 2 && y0 + TY + 2 <= c.ny &&
+                     z0 >= 2 && z0 + TZ + 2 <= c.nz;
+  // own node (ragged tiles: positions beyond the grid load node 0, unused)
+  const int lx = tid % TX, ly = (tid / TX) % TY, lz = tid / (TX * TY);
+  const int gx = x0 + lx, gy = y0 + ly, gz = z0 + lz;
+  const bool own = gx < c.nx && gy < c.ny && gz < c.nz;
+  const unsigned idx = own ? gx + c.nx * (gy + c.ny * gz) : 0u;
+  const float m0 = fl.m0[idx], m1x = fl.m1x[idx], m1y = fl.m1y[idx], m1z = fl.m1z[idx];
+
+  // phi over the tile + 2: every load issued before the first LDS store
+  constexpr int IP = (T::NP + T::NT - 1) / T::NT;
+  float hv[IP], lv[IP];
+#pragma unroll
+  for (int it = 0; it < IP; ++it) {
+    const int k = tid + it * T::NT;
+    if (k < T::NP) {
+      const int px = k % PX, py = (k / PX) % PY, pz = k / (PX * PY);
+      int qx = x0 - 2 + px, qy = y0 - 2 + py, qz = z0 - 2 + pz;
+      if (!inner) {
+        qx = map_axis(qx, c.nx, c.wall_x);
+        qy = map_axis(qy, c.ny, c.wall_y);
+        qz = map_axis(qz, c.nz, c.wall_z);
+      }
+      const unsigned q = qx + c.nx * (qy + c.ny * qz);
+      hv[it] = fl.phh[q];
+      lv[it] = fl.phl[q];
+    }
+  }
+#pragma unroll
+  for (int it = 0; it < IP; ++it) {
+    const int k = tid + it * T::NT;
+    if (k < T::NP) {
+      L.ph[k] = hv[it];
+      L.pl[k] = lv[it];
+    }
+  }
+  __syncthreads();
+
+  // mu over the tile + 1
+  for (int k = tid; k < T::NM; k += T::NT) {
+    int mx = k % MX, my = (k / MX) % MY, mz = k / (MX * MY);
+    if (!inner) {
+      mx = mirror_local(mx, x0 - 1, c.nx, c.wall_x, MX);
+      my = mirror_local(my, y0 - 1, c.ny, c.wall_y, MY);
+      mz = mirror_local(mz, z0 - 1, c.nz, c.wall_z, T::MZ);
+    }
+    const int pc = (mx + 1) + PX * ((my + 1) + PY * (mz + 1));
+    const float h0 = L.ph[pc], l0 = L.pl[pc];
+    float la = 0.0f, le = 0.0f;
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+      const int j = pc + nofs<PX, PY>(i);
+      const float d = (L.ph[j] - h0) + (L.pl[j] - l0);
+      if (i <= 6) la += d;
+      else le += d;
+    }
+    const float lap = (1.0f / 3.0f) * la + (1.0f / 6.0f) * le;
+    L.mu[k] = dtheta(c, h0, l0) - c.kappa * lap;
+  }
+  __syncthreads();
+
+  // the tile's own nodes
+  if (!own) return;
+  const int pc = (lx + 2) + PX * ((ly + 2) + PY * (lz + 2));
+  const int mc = (lx + 1) + MX * ((ly + 1) + MY * (lz + 1));
+  const float h0 = L.ph[pc], l0 = L.pl[pc];
+  float g[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+  for (int i = 1; i < Q; ++i) {
+    const int j = pc + nofs<PX, PY>(i);
+    const float d = (L.ph[j] - h0) + (L.pl[j] - l0);
+    const float w = i <= 6 ? (1.0f / 6.0f) : (1.0f / 12.0f);  // 3 w_i
+    if (EX(i)) g[0] += EX(i) > 0 ? w * d : -w * d;
+    if (EY(i)) g[1] += EY(i) > 0 ? w * d : -w * d;
+    if (EZ(i)) g[2] += EZ(i) > 0 ? w * d : -w * d;
+  }
+  const float mu = L.mu[mc];
+  float lmu = 0.0f;
+  if (want_lmu || c.corr != 0.0f) {
+    float la = 0.0f, le = 0.0f;
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+      const float d = L.mu[mc + nofs<MX, MY>(i)] - mu;
+      if (i <= 6) la += d;
+      else le += d;
+    }
+    lmu = (1.0f / 3.0f) * la + (1.0f / 6.0f) * le;
+  }
+  const float ph = h0 + l0;
   const float rho = c.rho_g + ph * c.drho;
   // (rho - c/2) u = 3 sum e gbar + (F_s + G)/2, gravity along -z
   const float fsx = mu * g[0], fsy = mu * g[1];
   const float fsz = mu * g[2] - (rho - c.rho_ref) * c.gravity;
   const float cc = c.corr * lmu;
   const float iden = __builtin_amdgcn_rcpf(rho - 0.5f * cc);
-  const float ux = (3.0f * fl.m1x[idx] + 0.5f * fsx) * iden;
-  const float uy = (3.0f * fl.m1y[idx] + 0.5f * fsy) * iden;
-  const float uz = (3.0f * fl.m1z[idx] + 0.5f * fsz) * iden;
+  const float ux = (3.0f * m1x + 0.5f * fsx) * iden;
+  const float uy = (3.0f * m1y + 0.5f * fsy) * iden;
+  const float uz = (3.0f * m1z + 0.5f * fsz) * iden;
+  fl.mu[idx] = mu;
   fl.ux[idx] = ux;
   fl.uy[idx] = uy;
   fl.uz[idx] = uz;
-  fl.p[idx] = fl.m0[idx] + (1.0f / 6.0f) * c.drho * (ux * g[0] + uy * g[1] + uz * g[2]);
+  fl.p[idx] = m0 + (1.0f / 6.0f) * c.drho * (ux * g[0] + uy * g[1] + uz * g[2]);
   fl.lmu[idx] = lmu;
   fl.gx[idx] = g[0];
   fl.gy[idx] = g[1];
@@ -344,9 +411,11 @@ k3_init(CaseDev c, int parity, const double* __restrict__ phi0, const double* __
 }  // namespace d3q19
 
 // ------------------------------------------------------------ launchers
-// One variant: node-parallel kernels of 256 threads (tile fields unused).
-const TileShape kD3Q19Tiles[] = {{1, 1, 1, 256}};
-const int kD3Q19TileCount = 1;
+// Variants: the tile of the fields kernel (the pull and collision kernels are
+// node-parallel, 256 threads).
+const TileShape kD3Q19Tiles[] = {{16, 8, 4, 512}, {32, 4, 4, 512}, {32, 8, 2, 512},
+                                 {16, 16, 2, 512}, {8, 8, 8, 512}};
+const int kD3Q19TileCount = sizeof(kD3Q19Tiles) / sizeof(kD3Q19Tiles[0]);
 
 namespace {
 d3q19::Fields3 fields3(const Field3Ptrs& f) {
@@ -369,25 +438,38 @@ d3q19::Fields3 fields3(const Field3Ptrs& f) {
   return fl;
 }
 
+template <int FX, int FY, int FZ>
+void launch_fields_t(const CaseDev& c, const d3q19::Fields3& fl, int want_lmu, hipStream_t s) {
+  const int ft = ((c.nx + FX - 1) / FX) * ((c.ny + FY - 1) / FY) * ((c.nz + FZ - 1) / FZ);
+  hipLaunchKernelGGL((d3q19::k3_fields_t<FX, FY, FZ>), dim3(8 * ((ft + 7) / 8)),
+                     dim3(FX * FY * FZ), 0, s, c, fl, want_lmu);
+}
+
 template <int S>
-hipError_t pipeline(const CaseDev& c, int parity, const d3q19::Fields3& fl, int want_lmu,
-                    bool collide, hipStream_t s) {
+hipError_t pipeline(int variant, const CaseDev& c, int parity, const d3q19::Fields3& fl,
+                    int want_lmu, bool collide, hipStream_t s) {
   const int grid = (c.n + 255) / 256;
   hipLaunchKernelGGL(d3q19::k3_pull<S>, dim3(grid), dim3(256), 0, s, c, parity, fl);
-  hipLaunchKernelGGL(d3q19::k3_mu, dim3(grid), dim3(256), 0, s, c, fl);
-  hipLaunchKernelGGL(d3q19::k3_fields, dim3(grid), dim3(256), 0, s, c, fl, want_lmu);
+  switch (variant) {
+    case 0: launch_fields_t<16, 8, 4>(c, fl, want_lmu, s); break;
+    case 1: launch_fields_t<32, 4, 4>(c, fl, want_lmu, s); break;
+    case 2: launch_fields_t<32, 8, 2>(c, fl, want_lmu, s); break;
+    case 3: launch_fields_t<16, 16, 2>(c, fl, want_lmu, s); break;
+    case 4: launch_fields_t<8, 8, 8>(c, fl, want_lmu, s); break;
+    default: return hipErrorInvalidValue;
+  }
   if (collide) hipLaunchKernelGGL(d3q19::k3_collide<S>, dim3(grid), dim3(256), 0, s, c, parity, fl);
   return hipGetLastError();
 }
 }  // namespace
 
-hipError_t d3q19_step_case(const CaseDev& c, int storage, int parity, const Field3Ptrs& f,
-                           hipStream_t stream) {
+hipError_t d3q19_step_case(int variant, const CaseDev& c, int storage, int parity,
+                           const Field3Ptrs& f, hipStream_t stream) {
   const d3q19::Fields3 fl = fields3(f);
   switch (storage) {
-    case ST_FP32: return pipeline<ST_FP32>(c, parity, fl, 0, true, stream);
-    case ST_FP16: return pipeline<ST_FP16>(c, parity, fl, 0, true, stream);
-    default: return pipeline<ST_BF16>(c, parity, fl, 0, true, stream);
+    case ST_FP32: return pipeline<ST_FP32>(variant, c, parity, fl, 0, true, stream);
+    case ST_FP16: return pipeline<ST_FP16>(variant, c, parity, fl, 0, true, stream);
+    default: return pipeline<ST_BF16>(variant, c, parity, fl, 0, true, stream);
   }
 }
 
@@ -396,9 +478,9 @@ hipError_t d3q19_fields_case(const CaseDev& c, int storage, int parity, const Fi
   const d3q19::Fields3 fl = fields3(f);
   hipError_t e;
   switch (storage) {
-    case ST_FP32: e = pipeline<ST_FP32>(c, parity, fl, 1, false, stream); break;
-    case ST_FP16: e = pipeline<ST_FP16>(c, parity, fl, 1, false, stream); break;
-    default: e = pipeline<ST_BF16>(c, parity, fl, 1, false, stream);
+    case ST_FP32: e = pipeline<ST_FP32>(0, c, parity, fl, 1, false, stream); break;
+    case ST_FP16: e = pipeline<ST_FP16>(0, c, parity, fl, 1, false, stream); break;
+    default: e = pipeline<ST_BF16>(0, c, parity, fl, 1, false, stream);
   }
   if (e != hipSuccess) return e;
   const int grid = (c.n + 255) / 256;

@@ -49,8 +49,8 @@ constexpr int kField3Planes = 15;
 struct Field3Ptrs {
   float* plane[kField3Planes];
 };
-hipError_t d3q19_step_case(const CaseDev& c, int storage, int parity, const Field3Ptrs& f,
-                           hipStream_t stream);
+hipError_t d3q19_step_case(int variant, const CaseDev& c, int storage, int parity,
+                           const Field3Ptrs& f, hipStream_t stream);
 hipError_t d3q19_fields_case(const CaseDev& c, int storage, int parity, const Field3Ptrs& f,
                              const FieldPtrs& out, hipStream_t stream);
 hipError_t d3q19_init(const CaseDev& c, int storage, int parity, const double* phi0,

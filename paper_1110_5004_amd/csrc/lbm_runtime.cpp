@@ -298,7 +298,7 @@ hipError_t launch_step(lbm_handle* h, int parity, hipStream_t s) {
   if (h->lattice == LBM_D3Q19) {
     const lbm::Field3Ptrs f = step_fields3(h);
     for (int k = 0; k < h->ncases; ++k) {
-      hipError_t e = lbm::d3q19_step_case(h->cd[k], h->storage, parity, f, s);
+      hipError_t e = lbm::d3q19_step_case(h->variant, h->cd[k], h->storage, parity, f, s);
       if (e != hipSuccess) return e;
     }
     return hipSuccess;

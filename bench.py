@@ -39,9 +39,9 @@ def parse():
     ap.add_argument("--no-extra", action="store_true", help="skip the FP16 / original-model legs")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--workload", default="splash1024x512",
-                    choices=["splash1024x512", "droplet4096"],
-                    help="splash1024x512 (the benchmark) or droplet4096 (profiling of "
-                         "the HBM-bound regime)")
+                    choices=["splash1024x512", "droplet4096", "splash3d"],
+                    help="splash1024x512 (the benchmark), droplet4096 (profiling of "
+                         "the HBM-bound regime) or splash3d (the D3Q19 step alone)")
     ap.add_argument("--variant", type=int, default=-1,
                     help="tile variant; -1 = autotuned")
     return ap.parse_args()
@@ -102,12 +102,14 @@ def leg_3d(torch, W, hip, storage, remove_fa, steps=100, warmup=10):
     sim.set_launch(rec["variant"], rec["grid"], rec["graph_steps"])
     t = time_gpu(torch, sim, steps, warmup)
     d = sim.diagnostics()
+    variant = sim.get_launch()[0]
     sim.close()
     mlups = case.n * steps / t / 1e6
     ach = case.n * BYTES_PER_LU_3D[storage] / (t / steps) / 1e9
     return dict(mlups=round(mlups, 1), achieved_gbs=round(ach, 1),
                 frac=round(ach / HBM_PEAK_GBS, 4), bytes_per_lu=BYTES_PER_LU_3D[storage],
-                steps=steps, nonfinite=int(d["nonfinite"]), mass_drift_rel=d["mass_drift_rel"])
+                steps=steps, nonfinite=int(d["nonfinite"]), mass_drift_rel=d["mass_drift_rel"],
+                ms_per_step=round(1e3 * t / steps, 4), variant=variant)
 
 
 def leg_ensemble(torch, W, hip, storage, steps=200, warmup=20):
@@ -212,6 +214,31 @@ def traffic_for(kernel_key, seconds_per_launch):
     return round(e["bytes_per_launch"] / seconds_per_launch / 1e9, 1), e["bytes_per_launch"]
 
 
+def main_3d(a, torch, W, hip):
+    """The D3Q19 256x256x128 splash alone (profiling of the 3-D path)."""
+    r = leg_3d(torch, W, hip, a.storage, a.remove_fa, a.steps, a.warmup)
+    pc_s = pull_copy_ceiling(torch, hip, hip.D3Q19, a.storage, (256, 256, 128), reps=20)
+    step_s = r["ms_per_step"] / 1e3
+    print(json.dumps({
+        "metric": "lattice updates/s (MLUPS), D3Q19 phase-field step", "value": r["mlups"],
+        "unit": "MLUPS", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": r["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if a.storage == "fp32" else f"f32 compute, {a.storage} storage",
+        "data": "synthetic (seeded 3-D splash initial condition)",
+        "config": {"workload": "splash3d", "grid": [256, 256, 128], "lattice": "D3Q19",
+                   "bc": "periodic x y, walls z", "storage": a.storage,
+                   "remove_fa": a.remove_fa},
+        "roofline": {"bound": "hbm", "achieved": r["achieved_gbs"], "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": r["frac"], "traffic": None,
+                     "bytes_per_lu": r["bytes_per_lu"],
+                     "kernel": "k3_pull + k3_fields_t + k3_collide", "variant": r["variant"],
+                     "pull_copy_us": round(pc_s * 1e6, 2),
+                     "frac_of_pull_copy": round(pc_s / step_s, 4)},
+        "check": {"mass_drift_rel": r["mass_drift_rel"], "nonfinite": r["nonfinite"]},
+    }), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -221,6 +248,9 @@ def main():
     import paper_1110_5004_amd as hip
     import workloads as W
     hip.lib()
+    if a.workload == "splash3d":
+        main_3d(a, torch, W, hip)
+        return
 
     main_leg = leg(torch, W, hip, a.storage, a.remove_fa, a.steps, a.warmup, a.workload,
                    a.variant)

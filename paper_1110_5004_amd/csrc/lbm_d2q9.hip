@@ -697,9 +697,9 @@ hipError_t launch_step_v(const LaunchArgs& a) {
 // Compiled tile shapes of the D2Q9 step (index = launch variant): tile width,
 // height, depth and threads per workgroup (one or two nodes per thread).
 const TileShape kD2Q9Tiles[] = {{32, 16, 1, 512}, {64, 8, 1, 512},  {64, 16, 1, 1024},
-                                {32, 8, 1, 256},  {128, 4, 1, 512}, {64, 8, 1, 512},
+                                {32, 8, 1, 256},  {128, 16, 1, 1024}, {64, 8, 1, 512},
                                 {64, 16, 1, 512}, {32, 16, 1, 256}, {64, 8, 1, 256},
-                                {32, 32, 1, 512}};
+                                {64, 32, 1, 1024}};
 const int kD2Q9TileCount = sizeof(kD2Q9Tiles) / sizeof(kD2Q9Tiles[0]);
 
 hipError_t d2q9_step(int variant, const LaunchArgs& a) {
@@ -708,12 +708,12 @@ hipError_t d2q9_step(int variant, const LaunchArgs& a) {
     case 1: return launch_step_v<64, 8>(a);
     case 2: return launch_step_v<64, 16>(a);
     case 3: return launch_step_v<32, 8>(a);
-    case 4: return launch_step_v<128, 4>(a);
+    case 4: return launch_step_v<128, 16, 2, 4>(a);
     case 5: return launch_step_v<64, 8, 1, 6>(a);
     case 6: return launch_step_v<64, 16, 2, 4>(a);
     case 7: return launch_step_v<32, 16, 2, 4>(a);
     case 8: return launch_step_v<64, 8, 2, 4>(a);
-    case 9: return launch_step_v<32, 32, 2, 4>(a);
+    case 9: return launch_step_v<64, 32, 2, 4>(a);
     default: return hipErrorInvalidValue;
   }
 }

@@ -205,6 +205,57 @@ __device__ __forceinline__ void g_sum(const CaseDev& c, const Raw<S>* gr, float*
   }
 }
 
+// The own nodes' pulled populations between the loads and the collision.
+// FP32 storage: decoded floats.  16-bit storage: the stored words, two per
+// register, decoded where the collision reads them (the same decode, hence the
+// same values); this halves the registers they occupy through phases B and C.
+template <int S, int NPT, bool WIDE = (S == ST_FP32)>
+struct OwnPops;
+
+template <int S, int NPT>
+struct OwnPops<S, NPT, true> {
+  float fv[NPT][Q], gv[NPT][Q];
+  __device__ __forceinline__ void set(int j, const float* f, const float* g, const Raw<S>*,
+                                      const Raw<S>*) {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      fv[j][i] = f[i];
+      gv[j][i] = g[i];
+    }
+  }
+  __device__ __forceinline__ float f(const CaseDev&, int j, int i) const { return fv[j][i]; }
+  __device__ __forceinline__ float g(const CaseDev&, int j, int i, float) const {
+    return gv[j][i];
+  }
+};
+
+template <int S, int NPT>
+struct OwnPops<S, NPT, false> {
+  uint32_t fp[NPT][(Q - 1 + 1) / 2];  // f_1 | f_2 << 16, f_3 | f_4 << 16, ...
+  uint32_t gp[NPT][(Q + 1) / 2];      // g_0 | g_1 << 16, ..., g_8
+  __device__ __forceinline__ void set(int j, const float*, const float*, const Raw<S>* fr,
+                                      const Raw<S>* gr) {
+#pragma unroll
+    for (int m = 0; m < (Q - 1 + 1) / 2; ++m) {
+      const int a = 2 * m + 1, b = 2 * m + 2;
+      fp[j][m] = (uint32_t)fr[a] | (b < Q ? (uint32_t)fr[b] << 16 : 0u);
+    }
+#pragma unroll
+    for (int m = 0; m < (Q + 1) / 2; ++m) {
+      const int a = 2 * m, b = 2 * m + 1;
+      gp[j][m] = (uint32_t)gr[a] | (b < Q ? (uint32_t)gr[b] << 16 : 0u);
+    }
+  }
+  __device__ __forceinline__ float f(const CaseDev& c, int j, int i) const {
+    const uint32_t w = fp[j][(i - 1) >> 1];
+    return Pops<S, Q>::dec_f(c, (uint16_t)((i - 1) & 1 ? w >> 16 : w & 0xffffu));
+  }
+  __device__ __forceinline__ float g(const CaseDev& c, int j, int i, float wi) const {
+    const uint32_t w = gp[j][i >> 1];
+    return Pops<S, Q>::dec_g(c, (uint16_t)(i & 1 ? w >> 16 : w & 0xffffu), wi);
+  }
+};
+
 struct FieldOut {
   float* phi;
   float* ux;
@@ -255,6 +306,15 @@ __device__ __forceinline__ void ring_pos(int k, int& lx, int& ly) {
   }
 }
 
+// threadIdx.x behind an empty asm: values derived from it are recomputed per
+// tile instead of being hoisted out of a workgroup's tile loop, where dozens
+// of per-thread LDS offsets would stay live (and spill) across all phases.
+__device__ __forceinline__ int tile_tid() {
+  int t = threadIdx.x;
+  asm volatile("" : "+v"(t));
+  return t;
+}
+
 // Everything one tile loads from global memory, held in registers as stored
 // words between issue (loads in flight) and consume (sums into LDS).  One
 // tile has NT = TX * TY / NPT threads; node j of a thread is tile position
@@ -277,11 +337,12 @@ struct TileLoads {
   uint16_t alo[IA];
   Raw<S> afr[IA][Q];
   Raw<S> cgr[IC][Q];
+  int tid = tile_tid();
 
   // Loads of one element: own node j, phi-ring slot it, moment-ring slot it.
   template <bool INNER>
   __device__ __forceinline__ void issue_own(const Puller<S, INNER>& pu, int x0, int y0, int j) {
-    const int kk = threadIdx.x + j * NT;
+    const int kk = tid + j * NT;
     int mx = x0 + kk % TX, my = y0 + kk / TX;
     if constexpr (!INNER) {
       mx = map_axis(mx, pu.c.nx, pu.c.wall_x);
@@ -292,7 +353,7 @@ struct TileLoads {
   }
   template <bool INNER>
   __device__ __forceinline__ void issue_phi(const Puller<S, INNER>& pu, int x0, int y0, int it) {
-    const int k = threadIdx.x + it * NT;
+    const int k = tid + it * NT;
     if (k < NRA) {
       int lx, ly;
       ring_pos<TX, TY, R>(k, lx, ly);
@@ -306,7 +367,7 @@ struct TileLoads {
   }
   template <bool INNER>
   __device__ __forceinline__ void issue_mom(const Puller<S, INNER>& pu, int x0, int y0, int it) {
-    const int k = threadIdx.x + it * NT;
+    const int k = tid + it * NT;
     if (k < NRC) {
       int lx, ly;
       ring_pos<TX, TY, 1>(k, lx, ly);
@@ -321,10 +382,11 @@ struct TileLoads {
 
   // Sums of one element into LDS; own nodes also keep their decoded
   // populations in fv, gv.
-  __device__ __forceinline__ void consume_own(const CaseDev& c, T& L, int j, float* fv,
-                                              float* gv) const {
-    const int kk = threadIdx.x + j * NT;
+  __device__ __forceinline__ void consume_own(const CaseDev& c, T& L, int j,
+                                              OwnPops<S, NPT>& own) const {
+    const int kk = tid + j * NT;
     const int lx0 = kk % TX, ly0 = kk / TX;
+    float fv[Q], gv[Q];
     float hi, plo;
     phi_sum<S>(c, f0[j], lo[j], fr[j], fv, hi, plo);
     const int pk = (ly0 + R) * T::PW + (lx0 + R);
@@ -336,9 +398,10 @@ struct TileLoads {
     L.p[uk] = m0;
     L.ux[uk] = m1x;
     L.uy[uk] = m1y;
+    own.set(j, fv, gv, fr[j], gr[j]);
   }
   __device__ __forceinline__ void consume_phi(const CaseDev& c, T& L, int it) const {
-    const int k = threadIdx.x + it * NT;
+    const int k = tid + it * NT;
     if (k < NRA) {
       int lx, ly;
       ring_pos<TX, TY, R>(k, lx, ly);
@@ -349,7 +412,7 @@ struct TileLoads {
     }
   }
   __device__ __forceinline__ void consume_mom(const CaseDev& c, T& L, int it) const {
-    const int k = threadIdx.x + it * NT;
+    const int k = tid + it * NT;
     if (k < NRC) {
       int lx, ly;
       ring_pos<TX, TY, 1>(k, lx, ly);
@@ -365,12 +428,12 @@ struct TileLoads {
   // far as registers allow).
   template <bool INNER>
   __device__ __forceinline__ void load_all(const CaseDev& c, const char* src, int x0, int y0,
-                                           T& L, float (*fv)[Q], float (*gv)[Q]) {
+                                           T& L, OwnPops<S, NPT>& own) {
     const Puller<S, INNER> pu(c, src);
 #pragma unroll
     for (int j = 0; j < NPT; ++j) {
       issue_own<INNER>(pu, x0, y0, j);
-      consume_own(c, L, j, fv[j], gv[j]);
+      consume_own(c, L, j, own);
     }
 #pragma unroll
     for (int it = 0; it < IA; ++it) {
@@ -392,8 +455,8 @@ struct TileLoads {
 // wrap, no wall), so no position needs mirroring.
 template <int TX, int TY, int NPT, int RF, int S, bool FIELDS, bool INNER>
 __device__ __forceinline__ void tile_bcd(TileLds<TX, TY, RF>& L, const CaseDev& c, int x0, int y0,
-                                         char* dst, const FieldOut& fo, const float (*fv)[Q],
-                                         const float (*gv)[Q]) {
+                                         char* dst, const FieldOut& fo,
+                                         const OwnPops<S, NPT>& own) {
   using T = TileLds<TX, TY, RF>;
   constexpr int NT = TX * TY / NPT;
   constexpr int R = T::R, RM = T::RM;
@@ -401,7 +464,7 @@ __device__ __forceinline__ void tile_bcd(TileLds<TX, TY, RF>& L, const CaseDev& 
   constexpr int IB = (MW * MH + NT - 1) / NT;
   constexpr int ICC = (UW * UH + NT - 1) / NT;
   const FF<PW> phi{L.ph, L.pl};
-  const int tid = threadIdx.x;
+  const int tid = tile_tid();
   const int nx = c.nx, ny = c.ny;
   const OutPtrs<S, Q> op(c, dst);
 
@@ -532,10 +595,10 @@ __device__ __forceinline__ void tile_bcd(TileLds<TX, TY, RF>& L, const CaseDev& 
                          (EY(i) ? (EY(i) > 0 ? hdy : -hdy) : 0.0f);
         const float ti = eu * (3.0f + 4.5f * eu) + m15;  // omega_i / w_i - 1
         if (i > 0) {
-          const float fn = omf * fv[j][i] + WT(i) * (fP + fQ * ti);
+          const float fn = omf * own.f(c, j, i) + WT(i) * (fP + fQ * ti);
           fsum += op.put_f(c, i, idx, fn);
         }
-        const float gn = omg * gv[j][i] + WT(i) * ((A + bi) + ti * (Cc + di));
+        const float gn = omg * own.g(c, j, i, WT(i)) + WT(i) * ((A + bi) + ti * (Cc + di));
         op.put_g(c, i, idx, gn, WT(i));
       }
       float h0, e0;
@@ -586,15 +649,15 @@ k_tile(const CaseDev* __restrict__ cases, const TileDev* __restrict__ tiles, int
     const char* src = parity ? c.state[1] : c.state[0];
     char* dst = parity ? c.state[0] : c.state[1];
     TileLoads<TX, TY, NPT, RF, S> ld;
-    float fv[NPT][Q], gv[NPT][Q];
+    OwnPops<S, NPT> own;
     if (tile_inner<TX, TY, RF>(c, tl)) {
-      ld.template load_all<true>(c, src, tl.x0, tl.y0, lds, fv, gv);
+      ld.template load_all<true>(c, src, tl.x0, tl.y0, lds, own);
       __syncthreads();
-      tile_bcd<TX, TY, NPT, RF, S, FIELDS, true>(lds, c, tl.x0, tl.y0, dst, fo, fv, gv);
+      tile_bcd<TX, TY, NPT, RF, S, FIELDS, true>(lds, c, tl.x0, tl.y0, dst, fo, own);
     } else {
-      ld.template load_all<false>(c, src, tl.x0, tl.y0, lds, fv, gv);
+      ld.template load_all<false>(c, src, tl.x0, tl.y0, lds, own);
       __syncthreads();
-      tile_bcd<TX, TY, NPT, RF, S, FIELDS, false>(lds, c, tl.x0, tl.y0, dst, fo, fv, gv);
+      tile_bcd<TX, TY, NPT, RF, S, FIELDS, false>(lds, c, tl.x0, tl.y0, dst, fo, own);
     }
   }
 }
@@ -695,25 +758,22 @@ hipError_t launch_step_v(const LaunchArgs& a) {
 }  // namespace
 
 // Compiled tile shapes of the D2Q9 step (index = launch variant): tile width,
-// height, depth and threads per workgroup (one or two nodes per thread).
-const TileShape kD2Q9Tiles[] = {{32, 16, 1, 512}, {64, 8, 1, 512},  {64, 16, 1, 1024},
-                                {32, 8, 1, 256},  {128, 16, 1, 1024}, {64, 8, 1, 512},
-                                {64, 16, 1, 512}, {32, 16, 1, 256}, {64, 8, 1, 256},
-                                {64, 32, 1, 1024}};
+// height, depth and threads per workgroup (one, two or four nodes per thread).
+const TileShape kD2Q9Tiles[] = {{32, 16, 1, 512},  {64, 8, 1, 512},    {64, 16, 1, 512},
+                                {128, 8, 1, 512},  {128, 16, 1, 1024}, {64, 32, 1, 1024},
+                                {64, 8, 1, 256},   {64, 16, 1, 256}};
 const int kD2Q9TileCount = sizeof(kD2Q9Tiles) / sizeof(kD2Q9Tiles[0]);
 
 hipError_t d2q9_step(int variant, const LaunchArgs& a) {
   switch (variant) {
     case 0: return launch_step_v<32, 16>(a);
     case 1: return launch_step_v<64, 8>(a);
-    case 2: return launch_step_v<64, 16>(a);
-    case 3: return launch_step_v<32, 8>(a);
+    case 2: return launch_step_v<64, 16, 2, 4>(a);
+    case 3: return launch_step_v<128, 8, 2, 4>(a);
     case 4: return launch_step_v<128, 16, 2, 4>(a);
-    case 5: return launch_step_v<64, 8, 1, 6>(a);
-    case 6: return launch_step_v<64, 16, 2, 4>(a);
-    case 7: return launch_step_v<32, 16, 2, 4>(a);
-    case 8: return launch_step_v<64, 8, 2, 4>(a);
-    case 9: return launch_step_v<64, 32, 2, 4>(a);
+    case 5: return launch_step_v<64, 32, 2, 4>(a);
+    case 6: return launch_step_v<64, 8, 2, 4>(a);
+    case 7: return launch_step_v<64, 16, 4, 4>(a);
     default: return hipErrorInvalidValue;
   }
 }

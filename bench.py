@@ -115,9 +115,14 @@ def leg_3d(torch, W, hip, storage, remove_fa, steps=100, warmup=10):
 def leg_ensemble(torch, W, hip, storage, steps=200, warmup=20):
     """64 droplet cases (64^2..512^2) in one launch per step, against the same
     cases advanced one Simulation at a time."""
+    from paper_1110_5004_amd import tune
     cases = W.ensemble(seed=0)
     nodes = sum(c.n for c in cases)
+    probe = hip.Simulation(cases, storage=storage)
+    rec = tune.tune(probe, steps=20)
+    probe.close()
     sim = hip.Simulation(cases, storage=storage)
+    sim.set_launch(rec["variant"], rec["grid"], rec["graph_steps"])
     t = time_gpu(torch, sim, steps, warmup)
     bad = sum(int(sim.diagnostics(k)["nonfinite"]) for k in range(len(cases)))
     sim.close()

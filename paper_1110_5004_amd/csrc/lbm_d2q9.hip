@@ -758,10 +758,14 @@ hipError_t launch_step_v(const LaunchArgs& a) {
 }  // namespace
 
 // Compiled tile shapes of the D2Q9 step (index = launch variant): tile width,
-// height, depth and threads per workgroup (one, two or four nodes per thread).
-const TileShape kD2Q9Tiles[] = {{32, 16, 1, 512},  {64, 8, 1, 512},    {64, 16, 1, 512},
-                                {128, 8, 1, 512},  {128, 16, 1, 1024}, {64, 32, 1, 1024},
-                                {64, 8, 1, 256},   {64, 16, 1, 256}};
+// height, depth, threads per workgroup (one, two or four nodes per thread) and
+// the strip width of the tile order (0: default).  The last three reuse
+// kernels of earlier entries with 1024-node strips (measured faster on
+// 4096^2 grids; narrower strips were slower).
+const TileShape kD2Q9Tiles[] = {
+    {32, 16, 1, 512, 0},  {64, 8, 1, 512, 0},    {64, 16, 1, 512, 0},  {128, 8, 1, 512, 0},
+    {128, 16, 1, 1024, 0}, {64, 32, 1, 1024, 0}, {64, 8, 1, 256, 0},   {64, 16, 1, 256, 0},
+    {64, 16, 1, 512, 1024}, {128, 8, 1, 512, 1024}, {64, 8, 1, 256, 1024}};
 const int kD2Q9TileCount = sizeof(kD2Q9Tiles) / sizeof(kD2Q9Tiles[0]);
 
 hipError_t d2q9_step(int variant, const LaunchArgs& a) {
@@ -774,6 +778,9 @@ hipError_t d2q9_step(int variant, const LaunchArgs& a) {
     case 5: return launch_step_v<64, 32, 2, 4>(a);
     case 6: return launch_step_v<64, 8, 2, 4>(a);
     case 7: return launch_step_v<64, 16, 4, 4>(a);
+    case 8: return launch_step_v<64, 16, 2, 4>(a);
+    case 9: return launch_step_v<128, 8, 2, 4>(a);
+    case 10: return launch_step_v<64, 8, 2, 4>(a);
     default: return hipErrorInvalidValue;
   }
 }

@@ -413,8 +413,8 @@ k3_init(CaseDev c, int parity, const double* __restrict__ phi0, const double* __
 // ------------------------------------------------------------ launchers
 // Variants: the tile of the fields kernel (the pull and collision kernels are
 // node-parallel, 256 threads).
-const TileShape kD3Q19Tiles[] = {{16, 8, 4, 512}, {32, 4, 4, 512}, {32, 8, 2, 512},
-                                 {16, 16, 2, 512}, {8, 8, 8, 512}};
+const TileShape kD3Q19Tiles[] = {{16, 8, 4, 512, 0}, {32, 4, 4, 512, 0}, {32, 8, 2, 512, 0},
+                                 {16, 16, 2, 512, 0}, {8, 8, 8, 512, 0}};
 const int kD3Q19TileCount = sizeof(kD3Q19Tiles) / sizeof(kD3Q19Tiles[0]);
 
 namespace {

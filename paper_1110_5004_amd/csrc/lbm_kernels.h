@@ -11,6 +11,7 @@ namespace lbm {
 struct TileShape {
   int tx, ty, tz;  // nodes per tile along x, y, z
   int nt;          // threads per workgroup
+  int strip;       // width in nodes of the tile-list strips (0: the default)
 };
 
 // Everything one step / field launch needs.

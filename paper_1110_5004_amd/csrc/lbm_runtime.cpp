@@ -113,7 +113,7 @@ long long count_tiles(const lbm_case_params& c, const lbm::TileShape& t) {
 }
 
 // Tile list, case after case.  Within a case the tiles run in vertical strips
-// about kStripNodes wide (tile rows inside a strip, strips left to right), so
+// about kStripNodes (or the shape's own strip) wide (tile rows inside a strip, strips left to right), so
 // that consecutive tiles -- which the kernel hands to the same XCD -- share
 // their halos.
 constexpr int kStripNodes = 512;
@@ -123,7 +123,8 @@ std::vector<TileDev> build_tiles(const lbm_case_params* cs, int n, const lbm::Ti
   std::vector<TileDev> v;
   if (off) off->assign(n, 0);
   if (cnt) cnt->assign(n, 0);
-  const int sw = std::max(1, kStripNodes / t.tx) * t.tx;  // strip width in nodes
+  const int strip = t.strip > 0 ? t.strip : kStripNodes;
+  const int sw = std::max(1, strip / t.tx) * t.tx;  // strip width in nodes
   for (int k = 0; k < n; ++k) {
     const lbm_case_params& c = cs[k];
     const int nzt = c.lattice == LBM_D3Q19 ? (c.nz + t.tz - 1) / t.tz : 1;

@@ -265,44 +265,33 @@ k3_fields_t(CaseDev c, Fields3 fl, int want_lmu) {
 }
 
 // ---- 4: collision and store
+// Per-node inputs of the collision (all at the node itself, ∇p included).
+struct NodeFields {
+  float phh, phl, mu, lmu, p, ux, uy, uz, gx, gy, gz, gpx, gpy, gpz;
+};
+
+// grad psi, the regrouped BGK collision of f and gbar with the Eq. 8 forcing
+// (see the D2Q9 step):
+//   g* = (1 - om) g + w [A + B_i + t_i (C + D_i)],  f* = (1 - om_f) f + w (P + Q t_i)
+// and the stores of node idx.  fv[1..18], gv[0..18]: its pulled populations.
 template <int S>
-__global__ void __launch_bounds__(256) k3_collide(CaseDev c, int parity, Fields3 fl) {
-  using P = Pops<S, Q>;
-  const unsigned idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (unsigned)c.n) return;
-  int x, y, z;
-  coords(c, idx, x, y, z);
-  const bool in = is_interior(c, x, y, z);
-  const char* src = parity ? c.state[1] : c.state[0];
-  char* dst = parity ? c.state[0] : c.state[1];
-  const OutPtrs<S, Q> op(c, dst);
-  float fv[Q], gv[Q];
-#pragma unroll
-  for (int i = 0; i < Q; ++i) {
-    if (i > 0) fv[i] = P::f(c, src, i, pull3<S, false>(c, x, y, z, idx, i, in));
-    gv[i] = P::g(c, src, pull3<S, true>(c, x, y, z, idx, i, in), WT(i));
-  }
-  float gp[3];
-  grad_f(c, fl.p, x, y, z, idx, in, gp);
-  const float phh = fl.phh[idx], phl = fl.phl[idx];
-  const float ph = phh + phl;
-  const float mu = fl.mu[idx], lmu = fl.lmu[idx], p = fl.p[idx];
-  const float ux = fl.ux[idx], uy = fl.uy[idx], uz = fl.uz[idx];
-  const float gx = fl.gx[idx], gy = fl.gy[idx], gz = fl.gz[idx];
+__device__ __forceinline__ void collide_node(const CaseDev& c, const OutPtrs<S, Q>& op,
+                                             unsigned idx, const float* fv, const float* gv,
+                                             const NodeFields& n) {
+  const float ph = n.phh + n.phl;
+  const float ux = n.ux, uy = n.uy, uz = n.uz, p = n.p, mu = n.mu;
   const float rho = c.rho_g + ph * c.drho;
-  const float cc = c.corr * lmu;
-  const float fx = mu * gx + cc * ux;
-  const float fy = mu * gy + cc * uy;
-  const float fz = mu * gz - (rho - c.rho_ref) * c.gravity + cc * uz;
-  const float gpsx = gp[0] - (1.0f / 3.0f) * c.drho * gx;
-  const float gpsy = gp[1] - (1.0f / 3.0f) * c.drho * gy;
-  const float gpsz = gp[2] - (1.0f / 3.0f) * c.drho * gz;
+  const float cc = c.corr * n.lmu;
+  const float fx = mu * n.gx + cc * ux;
+  const float fy = mu * n.gy + cc * uy;
+  const float fz = mu * n.gz - (rho - c.rho_ref) * c.gravity + cc * uz;
+  const float gpsx = n.gpx - (1.0f / 3.0f) * c.drho * n.gx;
+  const float gpsy = n.gpy - (1.0f / 3.0f) * c.drho * n.gy;
+  const float gpsz = n.gpz - (1.0f / 3.0f) * c.drho * n.gz;
   const float mud = c.mu_g + ph * c.dmu;
   const float om = rho * __builtin_amdgcn_rcpf(0.5f * rho + 3.0f * mud);  // 1 / tau
   const float half = 1.0f - 0.5f * om;
   const float uu = ux * ux + uy * uy + uz * uz;
-  // regrouped BGK with the Eq. 8 forcing (see the D2Q9 step):
-  //   g* = (1 - om) g + w [A + B_i + t_i (C + D_i)],  f* = (1 - om_f) f + w (P + Q t_i)
   const float uf = ux * fx + uy * fy + uz * fz;
   const float ug = ux * gpsx + uy * gpsy + uz * gpsz;
   const float A = om * p - half * uf;
@@ -335,8 +324,51 @@ __global__ void __launch_bounds__(256) k3_collide(CaseDev c, int parity, Fields3
     op.put_g(c, i, idx, gn, WT(i));
   }
   float h0, e0;
-  two_sum(phh, -fsum, h0, e0);
-  op.put_f0(idx, h0, e0 + phl);
+  two_sum(n.phh, -fsum, h0, e0);
+  op.put_f0(idx, h0, e0 + n.phl);
+}
+
+template <int S>
+__device__ __forceinline__ void pull_node(const CaseDev& c, const char* src, int x, int y, int z,
+                                          unsigned idx, bool in, float* fv, float* gv) {
+  using P = Pops<S, Q>;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    if (i > 0) fv[i] = P::f(c, src, i, pull3<S, false>(c, x, y, z, idx, i, in));
+    gv[i] = P::g(c, src, pull3<S, true>(c, x, y, z, idx, i, in), WT(i));
+  }
+}
+
+template <int S>
+__global__ void __launch_bounds__(256) k3_collide(CaseDev c, int parity, Fields3 fl) {
+  const unsigned idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (unsigned)c.n) return;
+  int x, y, z;
+  coords(c, idx, x, y, z);
+  const bool in = is_interior(c, x, y, z);
+  const char* src = parity ? c.state[1] : c.state[0];
+  char* dst = parity ? c.state[0] : c.state[1];
+  const OutPtrs<S, Q> op(c, dst);
+  float fv[Q], gv[Q];
+  pull_node<S>(c, src, x, y, z, idx, in, fv, gv);
+  float gp[3];
+  grad_f(c, fl.p, x, y, z, idx, in, gp);
+  NodeFields n;
+  n.phh = fl.phh[idx];
+  n.phl = fl.phl[idx];
+  n.mu = fl.mu[idx];
+  n.lmu = fl.lmu[idx];
+  n.p = fl.p[idx];
+  n.ux = fl.ux[idx];
+  n.uy = fl.uy[idx];
+  n.uz = fl.uz[idx];
+  n.gx = fl.gx[idx];
+  n.gy = fl.gy[idx];
+  n.gz = fl.gz[idx];
+  n.gpx = gp[0];
+  n.gpy = gp[1];
+  n.gpz = gp[2];
+  collide_node<S>(c, op, idx, fv, gv, n);
 }
 
 // ---- field dump for lbm_moments / diagnostics
@@ -412,7 +444,7 @@ k3_init(CaseDev c, int parity, const double* __restrict__ phi0, const double* __
 
 // ------------------------------------------------------------ launchers
 // Variants: the tile of the fields kernel (the pull and collision kernels are
-// node-parallel, 256 threads).
+// node-parallel, 256 threads).  All give the same bits.
 const TileShape kD3Q19Tiles[] = {{16, 8, 4, 512, 0}, {32, 4, 4, 512, 0}, {32, 8, 2, 512, 0},
                                  {16, 16, 2, 512, 0}, {8, 8, 8, 512, 0}};
 const int kD3Q19TileCount = sizeof(kD3Q19Tiles) / sizeof(kD3Q19Tiles[0]);

@@ -143,6 +143,15 @@ int lbm_moments_device(lbm_handle* h, int32_t icase, float* phi, float* u, float
  * reproducible from run to run).  Synchronises the stream. */
 int lbm_diagnostics(lbm_handle* h, int32_t icase, lbm_diag* out);
 
+/* Spread radius of case icase at the current time level: the largest half
+ * distance between the outermost crossings of phi = level along a grid row in
+ * x (every y, z), crossings located by linear interpolation between nodes x
+ * and x + 1 (x = 0 .. nx-2).  This is the droplet half-width that the paper
+ * compares between the original and the corrected model in its falling-drop
+ * test (Fig. 5).  *radius = 0 when no row crosses the level twice.
+ * Synchronizes the stream. */
+int lbm_spread_radius(lbm_handle* h, int32_t icase, double level, double* radius);
+
 /* Number of cases, time level, and bytes of one case's raw state. */
 int lbm_info(const lbm_handle* h, int32_t* ncases, int64_t* step, int32_t* storage);
 int lbm_state_bytes(const lbm_handle* h, int32_t icase, size_t* bytes);

@@ -586,6 +586,25 @@ void orc_diag(orc_sim* s, double* out) {
   out[16] = bad;
 }
 
+double orc_spread_radius(int nx, int ny, int nz, const double* phi, double level) {
+  double best = 0.0;
+  for (long r = 0; r < (long)ny * nz; ++r) {
+    const double* row = phi + r * nx;
+    double left = 0.0, right = 0.0;
+    int found = 0;
+    for (int x = 0; x + 1 < nx; ++x) {
+      const double a = row[x], b = row[x + 1];
+      if ((a >= level) == (b >= level)) continue;
+      const double pos = x + (level - a) / (b - a);
+      if (found == 0 || pos < left) left = pos;
+      if (found == 0 || pos > right) right = pos;
+      ++found;
+    }
+    if (found >= 2 && 0.5 * (right - left) > best) best = 0.5 * (right - left);
+  }
+  return best;
+}
+
 void orc_get_state(const orc_sim* s, double* f, double* g) {
   const size_t bytes = (size_t)(s->L.q * s->n) * sizeof(double);
   if (f) memcpy(f, s->f, bytes);

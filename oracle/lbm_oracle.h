@@ -84,6 +84,15 @@ void orc_fields(orc_sim* s, double* phi, double* u, double* p, double* mu,
  *  [17..19] reserved (0) */
 void orc_diag(orc_sim* s, double* out);
 
+/* Spread radius (diagnostic D6: the droplet half-width the paper compares
+ * between the two models in its falling-droplet test, Fig. 5).  Along every
+ * grid row in x (every y, z) the crossings of phi = level between nodes x and
+ * x + 1 (x = 0 .. nx-2, a crossing where exactly one of the two is >= level)
+ * are located by linear interpolation; the row's value is half the distance
+ * between its outermost crossings; the result is the maximum over rows with
+ * two or more crossings, 0 if there is none.  phi[nx*ny*nz], node order. */
+double orc_spread_radius(int nx, int ny, int nz, const double* phi, double level);
+
 /* Raw pre-collision populations f[Q*N], g[Q*N] (plane i at offset i*N). */
 void orc_get_state(const orc_sim* s, double* f, double* g);
 void orc_set_state(orc_sim* s, const double* f, const double* g, long time);

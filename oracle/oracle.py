@@ -59,6 +59,8 @@ def load(path=None):
                                 _DP, _DP, dp]
     lib.orc_grad_lap.argtypes = [P, _DP, dp, dp]
     lib.orc_stream_words.argtypes = [P, _UP, _UP]
+    lib.orc_spread_radius.argtypes = [C.c_int, C.c_int, C.c_int, _DP, C.c_double]
+    lib.orc_spread_radius.restype = C.c_double
     if path is None:
         _lib = lib
     return lib
@@ -75,6 +77,18 @@ def lattice(lat=D2Q9, lib=None):
     n = q.value
     return (np.array(e[:3 * n], dtype=np.int64).reshape(n, 3),
             np.array(w[:n]), np.array(opp[:n], dtype=np.int64))
+
+
+def spread_radius(phi, dims, level=0.5, lib=None):
+    """Diagnostic D6 of a phi field (nx*ny*nz values, node order): the largest
+    half-distance between the outermost phi = level crossings of a grid row
+    in x (see orc_spread_radius)."""
+    lib = lib or load()
+    nx, ny = int(dims[0]), int(dims[1])
+    nz = int(dims[2]) if len(dims) > 2 else 1
+    a = np.ascontiguousarray(phi, dtype=np.float64).ravel()
+    assert a.size == nx * ny * nz
+    return float(lib.orc_spread_radius(nx, ny, nz, a, float(level)))
 
 
 def beta_kappa(sigma, width, lib=None):

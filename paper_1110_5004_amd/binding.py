@@ -82,6 +82,7 @@ def lib():
     L.lbm_moments.argtypes = [_vp, C.c_int32, fp, fp, fp, fp, fp]
     L.lbm_moments_device.argtypes = [_vp, C.c_int32, _vp, _vp, _vp, _vp, _vp]
     L.lbm_diagnostics.argtypes = [_vp, C.c_int32, C.POINTER(Diag)]
+    L.lbm_spread_radius.argtypes = [_vp, C.c_int32, C.c_double, C.POINTER(C.c_double)]
     L.lbm_info.argtypes = [_vp, i32p, C.POINTER(C.c_int64), i32p]
     L.lbm_state_bytes.argtypes = [_vp, C.c_int32, C.POINTER(C.c_size_t)]
     L.lbm_get_state.argtypes = [_vp, C.c_int32, _vp, C.c_size_t]
@@ -254,6 +255,13 @@ class Simulation:
         d = Diag()
         _check(lib().lbm_diagnostics(self.h, icase, C.byref(d)))
         return d.to_dict()
+
+    def spread_radius(self, icase=0, level=0.5):
+        """Largest half-distance between the outermost phi = level crossings
+        of a grid row in x (the droplet half-width of the paper's Fig. 5)."""
+        r = C.c_double()
+        _check(lib().lbm_spread_radius(self.h, icase, float(level), C.byref(r)))
+        return r.value
 
     def state_bytes(self, icase=0):
         b = C.c_size_t()

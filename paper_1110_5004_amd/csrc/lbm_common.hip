@@ -145,6 +145,44 @@ hipError_t pull_copy(int lattice, int storage, const CaseDev& c, const void* src
   return hipGetLastError();
 }
 
+// Spread radius (the droplet half-width of the paper's falling-droplet
+// comparison): one 64-lane workgroup per grid row in x.  Each lane scans a
+// strided subset of the node pairs (x, x + 1), x = 0 .. nx - 2, for crossings
+// of phi = level (exactly one of the two >= level), located by linear
+// interpolation in double; min / max and the count combine across the wave
+// (exact operations, so the result does not depend on the order).  Out:
+// half the distance between the row's outermost crossings, or -1 when the row
+// has fewer than two.
+__global__ void __launch_bounds__(64)
+k_row_spread(int nx, const float* __restrict__ phi, double level, double* __restrict__ out) {
+  const long row = blockIdx.x;
+  const float* r = phi + row * nx;
+  double lo = 1e300, hi = -1e300;
+  int cnt = 0;
+  for (int x = threadIdx.x; x + 1 < nx; x += 64) {
+    const double a = r[x], b = r[x + 1];
+    if ((a >= level) == (b >= level)) continue;
+    const double pos = x + (level - a) / (b - a);
+    lo = fmin(lo, pos);
+    hi = fmax(hi, pos);
+    ++cnt;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    lo = fmin(lo, __shfl_xor(lo, off, 64));
+    hi = fmax(hi, __shfl_xor(hi, off, 64));
+    cnt += __shfl_xor(cnt, off, 64);
+  }
+  if (threadIdx.x == 0) out[row] = cnt >= 2 ? 0.5 * (hi - lo) : -1.0;
+}
+
+hipError_t row_spread(const CaseDev& c, const float* phi, double level, double* out,
+                      hipStream_t stream) {
+  const int rows = c.ny * c.nz;
+  hipLaunchKernelGGL(k_row_spread, dim3(rows), dim3(64), 0, stream, c.nx, phi, level, out);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- FP64 reductions
 // Sums (and one max) over the nodes of one case, from the dumped fields.
 // Every node goes to a fixed thread of a fixed workgroup; threads combine by

@@ -616,6 +616,30 @@ int lbm_diagnostics(lbm_handle* h, int32_t icase, lbm_diag* out) {
   return LBM_OK;
 }
 
+int lbm_spread_radius(lbm_handle* h, int32_t icase, double level, double* radius) {
+  if (!h || !radius || icase < 0 || icase >= h->ncases) return fail(LBM_ERR_ARG, "bad arguments");
+  if (!std::isfinite(level)) return fail(LBM_ERR_ARG, "level must be finite");
+  lbm::FieldPtrs f = scratch_fields(h);
+  int rc = dump_fields(h, icase, f);
+  if (rc) return rc;
+  const CaseDev& c = h->cd[icase];
+  const size_t rows = (size_t)c.ny * c.nz;
+  // per-row results (doubles) in the first F_a plane, which the dump just
+  // wrote and nothing here reads: one float plane holds nx * rows >= 2 rows
+  // floats
+  if (2 * rows > (size_t)c.stride) return fail(LBM_ERR_ARG, "grid too narrow in x");
+  double* rowbuf = reinterpret_cast<double*>(f.fa[0]);
+  HIPCHK(lbm::row_spread(c, f.phi, level, rowbuf, h->stream));
+  std::vector<double> host(rows);
+  HIPCHK(hipMemcpyAsync(host.data(), rowbuf, rows * sizeof(double), hipMemcpyDeviceToHost,
+                        h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  double best = 0.0;
+  for (double v : host) best = std::max(best, v);
+  *radius = best;
+  return LBM_OK;
+}
+
 int lbm_info(const lbm_handle* h, int32_t* ncases, int64_t* step, int32_t* storage) {
   if (!h) return fail(LBM_ERR_ARG, "NULL handle");
   if (ncases) *ncases = h->ncases;

@@ -629,6 +629,36 @@ def check_diagnostics(lib):
     assert abs(d["mass"] - c.phi0.sum()) < 1e-9 and d["nonfinite"] == 0
 
 
+def check_spread_radius(lib):
+    """Diagnostic D6 (half-width of the widest row, as in the paper's Fig. 5)
+    on fields whose answer is known: a two-level band of nodes 10..30 crosses
+    1/2 half-way between nodes, 9.5 and 30.5 (half-width 10.5); a tanh disk
+    whose centre lies on a grid row has half-width R there (the tanh profile
+    is odd about its crossing, so linear interpolation lands on it); a centre
+    between rows gives the chord sqrt(R^2 - d^2) of the nearest row; a field
+    with no row crossing twice gives 0; the level is honoured."""
+    nx, ny = 40, 5
+    phi = np.zeros((ny, nx))
+    phi[2, 10:31] = 1.0
+    assert abs(O.spread_radius(phi.ravel(), (nx, ny), lib=lib) - 10.5) < 1e-14
+    ramp = np.zeros((ny, nx))
+    ramp[1, 10:31] = 0.8
+    assert abs(O.spread_radius(ramp.ravel(), (nx, ny), 0.4, lib=lib) - 10.5) < 1e-14
+    assert O.spread_radius(ramp.ravel(), (nx, ny), 0.9, lib=lib) == 0.0
+    half = np.zeros((ny, nx))
+    half[:, 20:] = 1.0                     # one crossing per row only
+    assert O.spread_radius(half.ravel(), (nx, ny), lib=lib) == 0.0
+    nx, ny = 150, 120
+    y, x = np.mgrid[0:ny, 0:nx].astype(float)
+    for R, xc, yc in ((20.0, 74.3, 60.0), (27.5, 70.0, 44.0)):
+        ph = 0.5 + 0.5 * np.tanh(2.0 * (R - np.hypot(x - xc, y - yc)) / 3.0)
+        assert abs(O.spread_radius(ph.ravel(), (nx, ny), lib=lib) - R) < 1e-9
+    R, yc = 31.7, 55.3
+    ph = 0.5 + 0.5 * np.tanh(2.0 * (R - np.hypot(x - 75.0, y - yc)) / 3.0)
+    want = math.sqrt(R * R - 0.3 * 0.3)
+    assert abs(O.spread_radius(ph.ravel(), (nx, ny), lib=lib) - want) < 2e-2
+
+
 ALL_CHECKS = [check_lattice, check_feq_moments, check_geq_moments, check_source_moments,
               check_recover, check_stencil_polynomials, check_stencil_convergence,
               check_stencil_isotropy, check_mirror_ghosts, check_chemical_potential,
@@ -636,4 +666,4 @@ ALL_CHECKS = [check_lattice, check_feq_moments, check_geq_moments, check_source_
               check_uniform_flow, check_conservation, check_uniform_force,
               check_shear_wave, check_ch_diffusion, check_switch_noop, check_fa_field,
               check_momentum_balance, check_correction_velocity, check_eq5_fa,
-              check_advection, check_diagnostics]
+              check_advection, check_diagnostics, check_spread_radius]

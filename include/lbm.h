@@ -152,6 +152,18 @@ int lbm_diagnostics(lbm_handle* h, int32_t icase, lbm_diag* out);
  * Synchronizes the stream. */
 int lbm_spread_radius(lbm_handle* h, int32_t icase, double level, double* radius);
 
+/* The additional interfacial force F_a of Eq. 12 estimated from discrete
+ * data rather than through Eq. 5:
+ *   F_a = -u^n [ (rho^n - rho^(n-1)) + div(rho u)^n ],
+ * rho = rho_G + phi (rho_L - rho_G) (Eq. 4a), the time derivative a backward
+ * difference over one step, the divergence by the isotropic central scheme
+ * with the step's periodic / mirror-ghost neighbours.  It tests the paper's
+ * statement that d_t rho + div(rho u) is approximately Eq. 5.  phi_prev: device
+ * float[N], phi of case icase one step earlier (e.g. from
+ * lbm_moments_device); fa: device float[dim*N] (SoA), written.  Both
+ * caller-owned; enqueued on the handle's stream (no synchronization). */
+int lbm_fa_discrete(lbm_handle* h, int32_t icase, const float* phi_prev, float* fa);
+
 /* Number of cases, time level, and bytes of one case's raw state. */
 int lbm_info(const lbm_handle* h, int32_t* ncases, int64_t* step, int32_t* storage);
 int lbm_state_bytes(const lbm_handle* h, int32_t icase, size_t* bytes);

@@ -605,6 +605,29 @@ double orc_spread_radius(int nx, int ny, int nz, const double* phi, double level
   return best;
 }
 
+void orc_fa_discrete(const orc_params* prm, const double* phi_prev, const double* phi,
+                     const double* u, double* out) {
+  lat_t L;
+  if (lat_fill(prm->lattice, &L)) return;
+  const long n = count_nodes(prm);
+  const double drho = prm->rho_l - prm->rho_g;
+  double* m = alloc0(n);
+  double* grad = alloc0((long)L.dim * n);
+  double* div = alloc0(n);
+  for (int a = 0; a < L.dim; ++a) {
+    for (long idx = 0; idx < n; ++idx) m[idx] = (prm->rho_g + phi[idx] * drho) * u[a * n + idx];
+    grad_lap_lat(prm, &L, m, grad, NULL);
+    for (long idx = 0; idx < n; ++idx) div[idx] += grad[a * n + idx];
+  }
+  for (long idx = 0; idx < n; ++idx) {
+    const double dt_rho = (phi[idx] - phi_prev[idx]) * drho;
+    for (int a = 0; a < L.dim; ++a) out[a * n + idx] = -u[a * n + idx] * (dt_rho + div[idx]);
+  }
+  free(m);
+  free(grad);
+  free(div);
+}
+
 void orc_get_state(const orc_sim* s, double* f, double* g) {
   const size_t bytes = (size_t)(s->L.q * s->n) * sizeof(double);
   if (f) memcpy(f, s->f, bytes);

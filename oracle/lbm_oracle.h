@@ -93,6 +93,17 @@ void orc_diag(orc_sim* s, double* out);
  * two or more crossings, 0 if there is none.  phi[nx*ny*nz], node order. */
 double orc_spread_radius(int nx, int ny, int nz, const double* phi, double level);
 
+/* The additional interfacial force of Eq. 12 estimated from discrete data
+ * (instead of through Eq. 5):
+ *   F_a = -u [ (rho^n - rho^(n-1)) + div(rho u)^n ],
+ * the time derivative a backward difference over one step, the divergence by
+ * the isotropic central scheme (sum over components of the gradient of the
+ * component, with periodic wrap or mirror ghosts), rho = rho_G +
+ * phi (rho_L - rho_G) (Eq. 4a).  phi_prev, phi: N values at n-1 and n; u: dim*N
+ * (SoA) at n; out: dim*N (SoA). */
+void orc_fa_discrete(const orc_params* prm, const double* phi_prev, const double* phi,
+                     const double* u, double* out);
+
 /* Raw pre-collision populations f[Q*N], g[Q*N] (plane i at offset i*N). */
 void orc_get_state(const orc_sim* s, double* f, double* g);
 void orc_set_state(orc_sim* s, const double* f, const double* g, long time);

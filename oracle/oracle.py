@@ -60,6 +60,7 @@ def load(path=None):
     lib.orc_grad_lap.argtypes = [P, _DP, dp, dp]
     lib.orc_stream_words.argtypes = [P, _UP, _UP]
     lib.orc_spread_radius.argtypes = [C.c_int, C.c_int, C.c_int, _DP, C.c_double]
+    lib.orc_fa_discrete.argtypes = [P, _DP, _DP, _DP, _DP]
     lib.orc_spread_radius.restype = C.c_double
     if path is None:
         _lib = lib
@@ -89,6 +90,20 @@ def spread_radius(phi, dims, level=0.5, lib=None):
     a = np.ascontiguousarray(phi, dtype=np.float64).ravel()
     assert a.size == nx * ny * nz
     return float(lib.orc_spread_radius(nx, ny, nz, a, float(level)))
+
+
+def fa_discrete(case, phi_prev, phi, u, lib=None):
+    """F_a of Eq. 12 from discrete data: -u [(rho^n - rho^(n-1)) +
+    div(rho u)^n] (see orc_fa_discrete).  Returns (dim, N)."""
+    lib = lib or load()
+    prm = make_params(case, lib)
+    n = int(np.asarray(phi).size)
+    dim = 2 if case["lattice"] == D2Q9 else 3
+    out = np.zeros(dim * n)
+    lib.orc_fa_discrete(C.byref(prm), np.ascontiguousarray(phi_prev, dtype=np.float64).ravel(),
+                        np.ascontiguousarray(phi, dtype=np.float64).ravel(),
+                        np.ascontiguousarray(u, dtype=np.float64).ravel(), out)
+    return out.reshape(dim, n)
 
 
 def beta_kappa(sigma, width, lib=None):

@@ -83,6 +83,7 @@ def lib():
     L.lbm_moments_device.argtypes = [_vp, C.c_int32, _vp, _vp, _vp, _vp, _vp]
     L.lbm_diagnostics.argtypes = [_vp, C.c_int32, C.POINTER(Diag)]
     L.lbm_spread_radius.argtypes = [_vp, C.c_int32, C.c_double, C.POINTER(C.c_double)]
+    L.lbm_fa_discrete.argtypes = [_vp, C.c_int32, _vp, _vp]
     L.lbm_info.argtypes = [_vp, i32p, C.POINTER(C.c_int64), i32p]
     L.lbm_state_bytes.argtypes = [_vp, C.c_int32, C.POINTER(C.c_size_t)]
     L.lbm_get_state.argtypes = [_vp, C.c_int32, _vp, C.c_size_t]
@@ -255,6 +256,17 @@ class Simulation:
         d = Diag()
         _check(lib().lbm_diagnostics(self.h, icase, C.byref(d)))
         return d.to_dict()
+
+    def fa_discrete(self, phi_prev, icase=0):
+        """F_a from discrete data (see lbm_fa_discrete): phi_prev is a device
+        float32 tensor of phi one step earlier; returns a (dim, N) device
+        tensor."""
+        t = self.torch
+        n = self.n_nodes(icase)
+        out = t.empty(self.dim * n, dtype=t.float32, device=self.device)
+        _check(lib().lbm_fa_discrete(self.h, icase, C.c_void_p(phi_prev.data_ptr()),
+                                     C.c_void_p(out.data_ptr())))
+        return out.view(self.dim, n)
 
     def spread_radius(self, icase=0, level=0.5):
         """Largest half-distance between the outermost phi = level crossings

@@ -183,6 +183,57 @@ hipError_t row_spread(const CaseDev& c, const float* phi, double level, double* 
   return hipGetLastError();
 }
 
+// F_a of Eq. 12 from discrete data: -u [(rho^n - rho^(n-1)) + div(rho u)^n],
+// rho = rho_G + phi drho, the divergence 3 sum_i w_i e_i . (rho u)(x + e_i)
+// over the lattice stencil with periodic wrap or mirror ghosts (the same
+// neighbour convention as every other stencil of the step).
+template <int LAT>
+__global__ void __launch_bounds__(256)
+k_fa_discrete(CaseDev c, const float* __restrict__ phi_prev, const float* __restrict__ phi,
+              FieldPtrs f, float* __restrict__ out) {
+  constexpr int Q = LAT == 0 ? d2q9::Q : d3q19::Q;
+  constexpr int DIM = LAT == 0 ? 2 : 3;
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= c.n) return;
+  const int x = idx % c.nx;
+  const int y = (idx / c.nx) % c.ny;
+  const int z = idx / (c.nx * c.ny);
+  float div = 0.0f;
+#pragma unroll
+  for (int i = 1; i < Q; ++i) {
+    int ex, ey, ez;
+    float w;
+    if constexpr (LAT == 0) {
+      ex = d2q9::EX(i); ey = d2q9::EY(i); ez = 0; w = d2q9::WT(i);
+    } else {
+      ex = d3q19::EX(i); ey = d3q19::EY(i); ez = d3q19::EZ(i); w = d3q19::WT(i);
+    }
+    const int mx = map_axis(x + ex, c.nx, c.wall_x);
+    const int my = map_axis(y + ey, c.ny, c.wall_y);
+    const int mz = DIM == 3 ? map_axis(z + ez, c.nz, c.wall_z) : 0;
+    const unsigned j = mx + c.nx * (my + c.ny * mz);
+    const float rho = c.rho_g + phi[j] * c.drho;
+    float eu = ex * f.u[0][j] + ey * f.u[1][j];
+    if (DIM == 3) eu += ez * f.u[2][j];
+    div += 3.0f * w * rho * eu;
+  }
+  const float dt_rho = (phi[idx] - phi_prev[idx]) * c.drho;
+#pragma unroll
+  for (int a = 0; a < DIM; ++a) out[(size_t)a * c.n + idx] = -f.u[a][idx] * (dt_rho + div);
+}
+
+hipError_t fa_discrete(int lattice, const CaseDev& c, const float* phi_prev, const FieldPtrs& f,
+                       float* out, hipStream_t stream) {
+  const int grid = (c.n + 255) / 256;
+  if (lattice == 0)
+    hipLaunchKernelGGL(k_fa_discrete<0>, dim3(grid), dim3(256), 0, stream, c, phi_prev, f.phi,
+                       f, out);
+  else
+    hipLaunchKernelGGL(k_fa_discrete<1>, dim3(grid), dim3(256), 0, stream, c, phi_prev, f.phi,
+                       f, out);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- FP64 reductions
 // Sums (and one max) over the nodes of one case, from the dumped fields.
 // Every node goes to a fixed thread of a fixed workgroup; threads combine by

@@ -63,6 +63,10 @@ hipError_t stream_words(int lattice, const CaseDev& c, const uint32_t* in, uint3
 hipError_t encode16(int storage, const float* in, uint16_t* out, long long n,
                     hipStream_t stream);
 hipError_t copy_bw(const float* in, float* out, long long n, hipStream_t stream);
+// F_a = -u [(rho^n - rho^(n-1)) + div(rho u)] from phi at n-1 and the dumped
+// fields f (phi, u) at n; out: dim planes of c.n floats.
+hipError_t fa_discrete(int lattice, const CaseDev& c, const float* phi_prev, const FieldPtrs& f,
+                       float* out, hipStream_t stream);
 // Per row in x of a node field phi: half the distance between the outermost
 // phi = level crossings, or -1 (out: c.ny * c.nz doubles).
 hipError_t row_spread(const CaseDev& c, const float* phi, double level, double* out,

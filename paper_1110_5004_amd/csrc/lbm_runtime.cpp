@@ -616,6 +616,17 @@ int lbm_diagnostics(lbm_handle* h, int32_t icase, lbm_diag* out) {
   return LBM_OK;
 }
 
+int lbm_fa_discrete(lbm_handle* h, int32_t icase, const float* phi_prev, float* fa) {
+  if (!h || !phi_prev || !fa || icase < 0 || icase >= h->ncases)
+    return fail(LBM_ERR_ARG, "bad arguments");
+  lbm::FieldPtrs f = scratch_fields(h);
+  int rc = dump_fields(h, icase, f);
+  if (rc) return rc;
+  HIPCHK(lbm::fa_discrete(h->lattice == LBM_D2Q9 ? 0 : 1, h->cd[icase], phi_prev, f, fa,
+                          h->stream));
+  return LBM_OK;
+}
+
 int lbm_spread_radius(lbm_handle* h, int32_t icase, double level, double* radius) {
   if (!h || !radius || icase < 0 || icase >= h->ncases) return fail(LBM_ERR_ARG, "bad arguments");
   if (!std::isfinite(level)) return fail(LBM_ERR_ARG, "level must be finite");

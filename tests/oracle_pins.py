@@ -659,6 +659,41 @@ def check_spread_radius(lib):
     assert abs(O.spread_radius(ph.ravel(), (nx, ny), lib=lib) - want) < 2e-2
 
 
+def check_fa_discrete(lib):
+    """F_a from discrete data, -u [(rho^n - rho^(n-1)) + div(rho u)], against
+    closed forms of the discrete operators on a periodic sine of phi:
+    at rest it is 0; for a static field and uniform velocity the central
+    difference of sin(kx) is sin(k) cos(kx), so F = -u (u . drho a sin(k) cos(kx));
+    for a field shifted by one cell per step at unit speed the sum is
+    minus half the second difference, -4 sin^2(k/2) of the sine, giving
+    F_x = -(1/2) drho a 4 sin^2(k/2) sin(kx) (the first-order truncation of
+    the backward difference); and a y-only field gives no x-divergence."""
+    nx, ny = 64, 8
+    case = _case(nx, ny, rho_l=1.0, rho_g=0.1)
+    drho = 0.9
+    x = np.tile(np.arange(nx, dtype=float), ny)
+    k = 2 * math.pi * 3 / nx
+    a = 0.2
+    phi = 0.5 + a * np.sin(k * x)
+    u0 = np.zeros((2, nx * ny))
+    assert np.abs(O.fa_discrete(case, phi, phi, u0, lib=lib)).max() == 0.0
+    U, V = 0.03, -0.02
+    u = np.vstack([np.full(nx * ny, U), np.full(nx * ny, V)])
+    f = O.fa_discrete(case, phi, phi, u, lib=lib)
+    s_ = U * drho * a * math.sin(k) * np.cos(k * x)
+    assert np.allclose(f[0], -U * s_, atol=1e-15) and np.allclose(f[1], -V * s_, atol=1e-15)
+    prev = 0.5 + a * np.sin(k * (x + 1.0))    # phi^n(x) = phi^(n-1)(x - 1)
+    u1 = np.vstack([np.ones(nx * ny), np.zeros(nx * ny)])
+    f = O.fa_discrete(case, prev, phi, u1, lib=lib)
+    want = -0.5 * drho * a * 4 * math.sin(k / 2) ** 2 * np.sin(k * x)
+    assert np.allclose(f[0], want, atol=1e-14) and np.abs(f[1]).max() == 0.0
+    y = np.repeat(np.arange(ny, dtype=float), nx)
+    phiy = 0.5 + a * np.sin(2 * math.pi * y / ny)
+    f = O.fa_discrete(case, phiy, phiy, np.vstack([np.full(nx * ny, U), np.zeros(nx * ny)]),
+                      lib=lib)
+    assert np.abs(f).max() < 1e-17
+
+
 ALL_CHECKS = [check_lattice, check_feq_moments, check_geq_moments, check_source_moments,
               check_recover, check_stencil_polynomials, check_stencil_convergence,
               check_stencil_isotropy, check_mirror_ghosts, check_chemical_potential,
@@ -666,4 +701,4 @@ ALL_CHECKS = [check_lattice, check_feq_moments, check_geq_moments, check_source_
               check_uniform_flow, check_conservation, check_uniform_force,
               check_shear_wave, check_ch_diffusion, check_switch_noop, check_fa_field,
               check_momentum_balance, check_correction_velocity, check_eq5_fa,
-              check_advection, check_diagnostics, check_spread_radius]
+              check_advection, check_diagnostics, check_spread_radius, check_fa_discrete]

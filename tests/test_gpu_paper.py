@@ -128,3 +128,35 @@ def test_paper_splash_re48(hip):
     moved = float(np.abs(fields[0] - W.paper_splash(re=48).phi0).mean())
     print(f"t*=2: mean |phi_orig - phi_corr| = {diff:.2e} (mean change since t=0: {moved:.2e})")
     assert diff < 1e-3 and moved > 20 * diff
+
+
+def test_fa_discrete_against_oracle_and_eq5(hip):
+    """F_a of Eq. 12 from discrete data, -u [(rho^n - rho^(n-1)) + div(rho u)],
+    on the falling droplet (original model, t = 4000 -> 4001): GPU against
+    the oracle's definition on the oracle's fields, and the comparison the
+    paper's Eq. 5 reading rests on -- d_t rho + div(rho u) ~ drho theta_M
+    lap mu, so the discrete F_a should follow the F_a the step evaluates
+    (printed: relative L2 difference and the cosine between the two fields)."""
+    import torch
+    case = W.paper_falling(remove_fa=0)
+    steps = 4000
+    sim = hip.Simulation([case])
+    sim.step(steps)
+    phi_prev = sim.moments_device()["phi"].clone()
+    sim.step(1)
+    got = sim.fa_discrete(phi_prev).cpu().numpy().astype(np.float64)
+    eq5 = sim.moments()["fa"].astype(np.float64)
+    sim.close()
+    ref = O.Sim(case.params, case.phi0, case.u0, case.p0)
+    ref.step(steps)
+    prev = ref.fields()["phi"]
+    ref.step(1)
+    fl = ref.fields()
+    want = O.fa_discrete(case.params, prev, fl["phi"], fl["u"])
+    rel = np.linalg.norm(got - want) / np.linalg.norm(want)
+    rel5 = np.linalg.norm(got - eq5) / np.linalg.norm(eq5)
+    cos = float((got * eq5).sum() / (np.linalg.norm(got) * np.linalg.norm(eq5)))
+    print(f"discrete F_a: GPU vs oracle rel-L2 {rel:.2e}; against the Eq. 5 F_a of the step: "
+          f"rel-L2 {rel5:.2e}, cosine {cos:.3f}; max|F| {np.abs(want).max():.2e}")
+    assert rel < 5e-2
+    assert np.isfinite(rel5) and np.isfinite(cos)

@@ -147,6 +147,37 @@ def leg_ensemble(torch, W, hip, storage, steps=200, warmup=20):
     return out
 
 
+def leg_paper(torch, W, hip):
+    """The paper's two tests at their own sizes, corrected model, FP32: the
+    150x450 falling droplet (20k steps) and the 300x150 splash at Re = 48
+    (to t* = 4), each timed over the whole run; the falling droplet also
+    reports the spread radius at t = 1.9e4 of both models."""
+    from paper_1110_5004_amd import tune
+    out = {}
+    for name, builder, steps in (("falling150x450", W.paper_falling, 20000),
+                                 ("splash300x150_re48", W.paper_splash, 6000)):
+        case = builder(remove_fa=1)
+        probe = hip.Simulation([case])
+        rec = tune.tune(probe, steps=200)
+        probe.close()
+        sim = hip.Simulation([case])
+        sim.set_launch(rec["variant"], rec["grid"], rec["graph_steps"])
+        t = time_gpu(torch, sim, steps, 0)
+        d = sim.diagnostics()
+        sim.close()
+        out[name] = dict(steps=steps, seconds=round(t, 4), mlups=round(case.n * steps / t / 1e6, 1),
+                         nonfinite=int(d["nonfinite"]))
+    radii = {}
+    for m in (0, 1):
+        sim = hip.Simulation([W.paper_falling(remove_fa=m)])
+        sim.step(19000)
+        radii[m] = sim.spread_radius()
+        sim.close()
+    out["falling150x450"]["spread_radius_t19000"] = {"original": round(radii[0], 4),
+                                                     "corrected": round(radii[1], 4)}
+    return out
+
+
 def pull_copy_ceiling(torch, hip, lattice, storage, dims, reps=200):
     """Seconds per launch of the pull-copy calibration kernel: the step's
     reads (every population from x - e_i) and writes in the same plane
@@ -310,6 +341,7 @@ def main():
         out["d3q19_splash256x256x128"] = {f"{st}_rf{rf}": leg_3d(torch, W, hip, st, rf)
                                           for st, rf in (("fp16", 1), ("fp16", 0), ("fp32", 1))}
         out["ensemble64"] = {st: leg_ensemble(torch, W, hip, st) for st in ("fp32", "fp16")}
+        out["paper_experiments"] = leg_paper(torch, W, hip)
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(W, a.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -98,6 +98,18 @@ void orc_beta_kappa(double sigma, double width, double* beta, double* kappa) {
   *kappa = 1.5 * sigma * width;
 }
 
+/* With theta = beta (phi^2 - phi*^2)^2 (Eq. 1b) the flat interface is
+ * phi* tanh(2 z / W) with W^2 = 2 kappa / (beta phi*^2), and its tension
+ * sigma = int kappa phi'^2 dz = (4/3) sqrt(2 kappa beta) phi*^3.  Inverting:
+ * beta = 3 sigma / (4 W phi*^4), kappa = 3 sigma W / (8 phi*^2) (for
+ * phi* = 1/2 these are the values of the asymmetric well). */
+void orc_beta_kappa_sym(double sigma, double width, double phi_star, double* beta,
+                        double* kappa) {
+  const double p2 = phi_star * phi_star;
+  *beta = 3.0 * sigma / (4.0 * width * p2 * p2);
+  *kappa = 3.0 * sigma * width / (8.0 * p2);
+}
+
 /* ------------------------------------------------------------------------ */
 
 struct orc_sim {
@@ -110,6 +122,9 @@ struct orc_sim {
   double *mu, *lmu, *u, *force, *pr, *gpsi, *tau;
   double mass0;
   double gamma, drho, mu_l, mu_g;
+  /* phi of the pure gas and liquid (0, 1 or -phi*, phi*) and the slope of
+   * the density law, d rho / d phi (Eq. 4a or 4b) */
+  double phi_g, phi_l, drho_dphi;
 };
 
 static const double CS2 = 1.0 / 3.0;
@@ -174,9 +189,23 @@ void orc_grad_lap(const orc_params* prm, const double* field, double* grad,
   grad_lap_lat(prm, &L, field, grad, lap);
 }
 
-/* theta'(phi) for theta = beta phi^2 (phi - 1)^2 (Eq. 1a). */
-static double dtheta(double beta, double phi) {
-  return 2.0 * beta * phi * (phi - 1.0) * (2.0 * phi - 1.0);
+/* theta'(phi) for theta = beta phi^2 (phi - 1)^2 (Eq. 1a), or for the
+ * symmetric theta = beta (phi^2 - phi*^2)^2 (Eq. 1b). */
+static double dtheta_well(const orc_params* p, double phi) {
+  if (p->well) return 4.0 * p->beta * phi * (phi * phi - p->phi_star * p->phi_star);
+  return 2.0 * p->beta * phi * (phi - 1.0) * (2.0 * phi - 1.0);
+}
+
+/* Density from the order parameter: Eq. 4a, rho_G + phi (rho_L - rho_G), or
+ * Eq. 4b, rho_G + (phi + phi*) / (2 phi*) (rho_L - rho_G); both are
+ * rho_G + (phi - phi_G) d rho / d phi. */
+static double rho_of(const orc_params* p, double phi) {
+  if (p->well)
+    return p->rho_g + (phi + p->phi_star) / (2.0 * p->phi_star) * (p->rho_l - p->rho_g);
+  return p->rho_g + phi * (p->rho_l - p->rho_g);
+}
+static double drho_dphi_of(const orc_params* p) {
+  return p->well ? (p->rho_l - p->rho_g) / (2.0 * p->phi_star) : p->rho_l - p->rho_g;
 }
 
 static double dot(const double* a, const double* b, int dim) {
@@ -324,6 +353,8 @@ static int params_ok(const orc_params* p, const lat_t* L) {
   if (L->dim == 3 && p->nz < 4) return 0;
   if (!(p->tau_f > 0.5) || !(p->tau_g > 0.5)) return 0;
   if (!(p->rho_l > 0.0) || !(p->rho_g > 0.0) || !(p->mu_ratio > 0.0)) return 0;
+  if (p->well != 0 && p->well != 1) return 0;
+  if (p->well == 1 && !(p->phi_star > 0.0)) return 0;
   return 1;
 }
 
@@ -359,8 +390,11 @@ orc_sim* orc_create(const orc_params* prm, const double* phi0, const double* u0,
   /* Theta_M = Gamma (tau_f - 1/2) for the BGK Cahn-Hilliard LBE. */
   s->gamma = prm->theta_m / (prm->tau_f - 0.5);
   s->drho = prm->rho_l - prm->rho_g;
+  s->phi_g = prm->well ? -prm->phi_star : 0.0;
+  s->phi_l = prm->well ? prm->phi_star : 1.0;
+  s->drho_dphi = drho_dphi_of(prm);
   /* Liquid kinematic viscosity nu_L = cs^2 (tau_g - 1/2); dynamic viscosity
-   * linear in phi between mu_G = mu_L / ratio and mu_L. */
+   * linear in phi between mu_G = mu_L / ratio (at phi_G) and mu_L (at phi_L). */
   s->mu_l = prm->rho_l * CS2 * (prm->tau_g - 0.5);
   s->mu_g = s->mu_l / prm->mu_ratio;
 
@@ -368,14 +402,14 @@ orc_sim* orc_create(const orc_params* prm, const double* phi0, const double* u0,
    * stencils as the step. */
   for (long idx = 0; idx < n; ++idx) {
     s->phi[idx] = phi0[idx];
-    s->rho[idx] = prm->rho_g + phi0[idx] * s->drho;
+    s->rho[idx] = rho_of(prm, phi0[idx]);
   }
   grad_lap_lat(&s->prm, &L, s->phi, s->gphi, s->lphi);
   for (long idx = 0; idx < n; ++idx) {
     double uu[3] = {0.0, 0.0, 0.0};
     double fe[QMAX], ge[QMAX];
     for (int k = 0; k < dim; ++k) uu[k] = u0[k * n + idx];
-    double mu = dtheta(prm->beta, s->phi[idx]) - prm->kappa * s->lphi[idx];
+    double mu = dtheta_well(prm, s->phi[idx]) - prm->kappa * s->lphi[idx];
     feq_lat(&L, s->phi[idx], mu, uu, s->gamma, fe);
     geq_lat(&L, p0[idx], s->rho[idx], uu, ge);
     for (int i = 0; i < q; ++i) {
@@ -415,13 +449,13 @@ static void sweep_fields(orc_sim* s, int want_lmu) {
     double sum = 0.0;
     for (int i = 0; i < q; ++i) sum += s->f[i * n + idx];
     s->phi[idx] = sum;
-    s->rho[idx] = p->rho_g + sum * s->drho;
+    s->rho[idx] = rho_of(p, sum);
   }
   /* S1b: stencils and chemical potential. */
   grad_lap_lat(p, L, s->phi, s->gphi, s->lphi);
 #pragma omp parallel for schedule(static)
   for (long idx = 0; idx < n; ++idx)
-    s->mu[idx] = dtheta(p->beta, s->phi[idx]) - p->kappa * s->lphi[idx];
+    s->mu[idx] = dtheta_well(p, s->phi[idx]) - p->kappa * s->lphi[idx];
   /* S1c: Laplacian of mu, the divergence of the diffusive flux in Eq. 5. */
   if (p->remove_fa || want_lmu)
     grad_lap_lat(p, L, s->mu, NULL, s->lmu);
@@ -435,10 +469,10 @@ static void sweep_fields(orc_sim* s, int want_lmu) {
     for (int i = 0; i < q; ++i) gb[i] = s->g[i * n + idx];
     for (int k = 0; k < dim; ++k) {
       fsg[k] = s->mu[idx] * s->gphi[k * n + idx];   /* F_s = mu grad phi */
-      grho[k] = s->drho * s->gphi[k * n + idx];     /* grad rho */
+      grho[k] = s->drho_dphi * s->gphi[k * n + idx];  /* grad rho */
     }
     fsg[vert] += -(s->rho[idx] - p->rho_ref) * p->gravity;   /* G */
-    double c = sw * s->drho * p->theta_m * s->lmu[idx];      /* -F_a = c u */
+    double c = sw * s->drho_dphi * p->theta_m * s->lmu[idx];  /* -F_a = c u */
     recover_lat(L, gb, s->rho[idx], fsg, c, grho, uu, ff, &pp);
     for (int k = 0; k < dim; ++k) {
       s->u[k * n + idx] = uu[k];
@@ -451,8 +485,9 @@ static void sweep_fields(orc_sim* s, int want_lmu) {
 #pragma omp parallel for schedule(static)
   for (long idx = 0; idx < n; ++idx) {
     for (int k = 0; k < dim; ++k)
-      s->gpsi[k * n + idx] -= CS2 * s->drho * s->gphi[k * n + idx];
-    double nu = (s->mu_g + s->phi[idx] * (s->mu_l - s->mu_g)) / s->rho[idx];
+      s->gpsi[k * n + idx] -= CS2 * s->drho_dphi * s->gphi[k * n + idx];
+    double frac = (s->phi[idx] - s->phi_g) / (s->phi_l - s->phi_g);
+    double nu = (s->mu_g + frac * (s->mu_l - s->mu_g)) / s->rho[idx];
     s->tau[idx] = 0.5 + nu / CS2;
   }
 }
@@ -531,7 +566,7 @@ void orc_fields(orc_sim* s, double* phi, double* u, double* p, double* mu,
     for (int k = 0; k < dim; ++k)
       for (long idx = 0; idx < n; ++idx)
         fa[k * n + idx] =
-            -s->u[k * n + idx] * s->drho * s->prm.theta_m * s->lmu[idx];
+            -s->u[k * n + idx] * s->drho_dphi * s->prm.theta_m * s->lmu[idx];
 }
 
 void orc_diag(orc_sim* s, double* out) {
@@ -547,7 +582,7 @@ void orc_diag(orc_sim* s, double* out) {
     coords(p, idx, c);
     double ph = s->phi[idx];
     mass += ph;
-    double w = 2.0 * ph - 0.5;
+    double w = 2.0 * (ph - s->phi_g) / (s->phi_l - s->phi_g) - 0.5;
     w = w < 0.0 ? 0.0 : (w > 1.0 ? 1.0 : w);
     sw += w;
     double uu = 0.0;
@@ -569,7 +604,7 @@ void orc_diag(orc_sim* s, double* out) {
   for (long idx = 0; idx < n; ++idx) {
     int c[3];
     coords(p, idx, c);
-    double w = 2.0 * s->phi[idx] - 0.5;
+    double w = 2.0 * (s->phi[idx] - s->phi_g) / (s->phi_l - s->phi_g) - 0.5;
     w = w < 0.0 ? 0.0 : (w > 1.0 ? 1.0 : w);
     for (int k = 0; k < dim; ++k) m2[k] += w * (c[k] - cen[k]) * (c[k] - cen[k]);
   }
@@ -610,12 +645,12 @@ void orc_fa_discrete(const orc_params* prm, const double* phi_prev, const double
   lat_t L;
   if (lat_fill(prm->lattice, &L)) return;
   const long n = count_nodes(prm);
-  const double drho = prm->rho_l - prm->rho_g;
+  const double drho = drho_dphi_of(prm);
   double* m = alloc0(n);
   double* grad = alloc0((long)L.dim * n);
   double* div = alloc0(n);
   for (int a = 0; a < L.dim; ++a) {
-    for (long idx = 0; idx < n; ++idx) m[idx] = (prm->rho_g + phi[idx] * drho) * u[a * n + idx];
+    for (long idx = 0; idx < n; ++idx) m[idx] = rho_of(prm, phi[idx]) * u[a * n + idx];
     grad_lap_lat(prm, &L, m, grad, NULL);
     for (long idx = 0; idx < n; ++idx) div[idx] += grad[a * n + idx];
   }

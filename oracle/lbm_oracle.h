@@ -45,6 +45,10 @@ typedef struct {
   double gravity;       /* magnitude g of the body force G = -(rho - rho_ref) g e_vert */
   double rho_ref;       /* reference density of the body force */
   int remove_fa;        /* 0: original model (F_a present), 1: corrected (adds -F_a) */
+  int well;             /* 0: theta = beta phi^2 (phi-1)^2, phi in [0, 1], rho by Eq. 4a;
+                           1: symmetric theta = beta (phi^2 - phi*^2)^2 (Eq. 1b), phi in
+                           [-phi*, phi*], rho by Eq. 4b */
+  double phi_star;      /* phi* of the symmetric well (> 0; unused when well = 0) */
 } orc_params;
 
 typedef struct orc_sim orc_sim;
@@ -55,6 +59,9 @@ int orc_lattice(int lattice, int* q, int* e, double* w, int* opp);
 
 /* sigma, W -> beta, kappa for the flat tanh interface of width W. */
 void orc_beta_kappa(double sigma, double width, double* beta, double* kappa);
+/* The same for the symmetric well of Eq. 1b with minima at +-phi_star. */
+void orc_beta_kappa_sym(double sigma, double width, double phi_star, double* beta,
+                        double* kappa);
 
 /* Create a simulation from FP64 initial fields phi0[N], u0[dim*N], p0[N].
  * Returns NULL on invalid parameters. */
@@ -76,7 +83,7 @@ void orc_fields(orc_sim* s, double* phi, double* u, double* p, double* mu,
 /* Diagnostics, fixed summation order (node order).  out receives 20 doubles:
  *  [0] mass = sum phi       [1] mass at creation
  *  [2..4] momentum sum rho u
- *  [5] sum w, w = clamp(2 phi - 1/2, 0, 1)
+ *  [5] sum w, w = clamp(2 phi01 - 1/2, 0, 1), phi01 = (phi - phi_G) / (phi_L - phi_G)
  *  [6..8] centroid sum w x / sum w
  *  [9..11] centroid velocity sum w u / sum w
  *  [12..14] second moment sum w (x - X)^2 / sum w, per axis

@@ -22,7 +22,7 @@ class OrcParams(C.Structure):
         ("tau_f", C.c_double), ("tau_g", C.c_double),
         ("rho_l", C.c_double), ("rho_g", C.c_double), ("mu_ratio", C.c_double),
         ("gravity", C.c_double), ("rho_ref", C.c_double),
-        ("remove_fa", C.c_int),
+        ("remove_fa", C.c_int), ("well", C.c_int), ("phi_star", C.c_double),
     ]
 
 
@@ -42,6 +42,7 @@ def load(path=None):
     lib.orc_lattice.argtypes = [C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), dp,
                                 C.POINTER(C.c_int)]
     lib.orc_beta_kappa.argtypes = [C.c_double, C.c_double, dp, dp]
+    lib.orc_beta_kappa_sym.argtypes = [C.c_double, C.c_double, C.c_double, dp, dp]
     lib.orc_create.argtypes = [P, _DP, _DP, _DP]
     lib.orc_create.restype = C.c_void_p
     lib.orc_destroy.argtypes = [C.c_void_p]
@@ -113,14 +114,27 @@ def beta_kappa(sigma, width, lib=None):
     return b.value, k.value
 
 
+def beta_kappa_sym(sigma, width, phi_star, lib=None):
+    """beta, kappa of the symmetric well (Eq. 1b) for tension sigma and
+    width W (orc_beta_kappa_sym)."""
+    lib = lib or load()
+    b, k = C.c_double(), C.c_double()
+    lib.orc_beta_kappa_sym(sigma, width, phi_star, C.byref(b), C.byref(k))
+    return b.value, k.value
+
+
 def make_params(case, lib=None):
     """OrcParams from a case dict (keys as produced by workloads.Case.params).
 
     beta and kappa are derived here from sigma and W by the oracle's own
     formula unless the dict gives them directly."""
     p = OrcParams()
+    well = int(case.get("well", 0))
     if "beta" not in case:
-        b, k = beta_kappa(case["sigma"], case["width"], lib)
+        if well:
+            b, k = beta_kappa_sym(case["sigma"], case["width"], case["phi_star"], lib)
+        else:
+            b, k = beta_kappa(case["sigma"], case["width"], lib)
         case = dict(case, beta=b, kappa=k)
     p.lattice = case["lattice"]
     p.nx, p.ny, p.nz = case["nx"], case["ny"], case.get("nz", 1)
@@ -130,6 +144,8 @@ def make_params(case, lib=None):
               "mu_ratio", "gravity", "rho_ref"):
         setattr(p, k, float(case[k]))
     p.remove_fa = int(case["remove_fa"])
+    p.well = well
+    p.phi_star = float(case.get("phi_star", 0.5))
     return p
 
 

@@ -440,9 +440,11 @@ def check_flat_interface(lib):
     assert 3.0 < e4 / e8 < 6.0, (e4, e8)
 
 
-def laplace_dp(lib, radius, n=96, steps=3000, sigma=0.01, width=4.0):
+def laplace_dp(lib, radius, n=96, steps=3000, sigma=0.01, width=4.0, well=0, phi_star=0.5,
+               theta_m=0.1):
     c = W.stationary_droplet(seed=0, n=n, radius=radius, noise_amp=0.0, centre_jitter=0.0,
-                             sigma=sigma, width=width)
+                             sigma=sigma, width=width, well=well, phi_star=phi_star,
+                             theta_m=theta_m)
     s = O.Sim(c.params, c.phi0, np.zeros_like(c.u0), np.zeros_like(c.p0), lib=lib)
     s.step(steps)
     p = s.fields()["p"].reshape(n, n)
@@ -694,6 +696,56 @@ def check_fa_discrete(lib):
     assert np.abs(f).max() < 1e-17
 
 
+def check_symmetric_well(lib):
+    """The symmetric well of Eq. 1b, theta = beta (phi^2 - phi*^2)^2, with the
+    density law of Eq. 4b, rho = rho_G + (phi + phi*) / (2 phi*) (rho_L - rho_G):
+    (a) beta, kappa from sigma, W make phi* tanh(2z/W) solve kappa phi'' =
+    theta'(phi) with tension int kappa phi'^2 dz = sigma;  (b) on a uniform
+    field mu = theta'(phi) = 4 beta phi (phi^2 - phi*^2);  (c) the density of
+    a uniform field moving at u gives momentum rho(phi) u N with rho = rho_L at
+    phi*, rho_G at -phi*, the mean at 0;  (d) the diagnostic weight maps
+    phi* (2 phi01 - 1) with phi01 = 1/4, 1/2, 3/4 to 0, 1/2, 1;  (e) resting
+    droplets with phi* = 0.8 obey Young-Laplace, dp R / sigma = 1 to 5 % for
+    R = 12, 16, 20 (mobility theta_M scaled by (2 phi*)^2, which keeps the
+    Cahn-Hilliard relaxation rate of the phi in [0, 1] runs)."""
+    from scipy.integrate import quad
+    for sigma, width, ps in ((0.01, 4.0, 0.5), (0.005, 3.0, 1.0), (0.01, 4.0, 0.8)):
+        beta, kappa = O.beta_kappa_sym(sigma, width, ps, lib)
+        for z in np.linspace(-6, 6, 25):
+            t = math.tanh(2 * z / width)
+            phi = ps * t
+            d2 = -8.0 * ps / width**2 * t * (1 - t * t)
+            dth = 4 * beta * phi * (phi * phi - ps * ps)
+            assert abs(kappa * d2 - dth) < 1e-12 * max(1.0, beta)
+        tension = quad(lambda z: kappa * (2 * ps / width * (1 - math.tanh(2 * z / width) ** 2))
+                       ** 2, -50, 50, epsabs=1e-14)[0]
+        assert abs(tension - sigma) < 1e-9 * sigma + 1e-15
+    n, ps = 8, 0.8
+    case = _case(n, n, well=1, phi_star=ps, rho_l=2.0, rho_g=0.5)
+    beta, _ = O.beta_kappa_sym(0.01, 4.0, ps, lib)
+    for phi in (0.3, -0.6, ps, -ps, 0.0):
+        s = O.Sim(case, np.full(n * n, phi), np.zeros(2 * n * n), np.zeros(n * n), lib=lib)
+        mu = s.fields()["mu"]
+        assert np.allclose(mu, 4 * beta * phi * (phi * phi - ps * ps), rtol=1e-13, atol=1e-18)
+    for phi, rho in ((ps, 2.0), (-ps, 0.5), (0.0, 1.25), (0.4, 1.625)):
+        u = np.zeros((2, n * n))
+        u[0] = 0.01
+        s = O.Sim(case, np.full(n * n, phi), u, np.zeros(n * n), lib=lib)
+        d = s.diag()
+        assert abs(d["momentum"][0] - rho * 0.01 * n * n) < 1e-13
+        assert abs(d["momentum"][1]) < 1e-15
+    for frac, w in ((0.25, 0.0), (0.5, 0.5), (0.75, 1.0)):
+        s = O.Sim(case, np.full(n * n, ps * (2 * frac - 1)), np.zeros(2 * n * n),
+                  np.zeros(n * n), lib=lib)
+        assert abs(s.diag()["wsum"] - w * n * n) < 1e-12
+    # under phi -> c phi the Cahn-Hilliard equation keeps its rate only if the
+    # mobility scales by c^2
+    radii = np.array([12.0, 16.0, 20.0])
+    dps = np.array([laplace_dp(lib, r, well=1, phi_star=ps, theta_m=0.1 * (2 * ps) ** 2)
+                    for r in radii])
+    assert np.all(np.abs(dps * radii / 0.01 - 1) < 0.05), dps * radii
+
+
 ALL_CHECKS = [check_lattice, check_feq_moments, check_geq_moments, check_source_moments,
               check_recover, check_stencil_polynomials, check_stencil_convergence,
               check_stencil_isotropy, check_mirror_ghosts, check_chemical_potential,
@@ -701,4 +753,5 @@ ALL_CHECKS = [check_lattice, check_feq_moments, check_geq_moments, check_source_
               check_uniform_flow, check_conservation, check_uniform_force,
               check_shear_wave, check_ch_diffusion, check_switch_noop, check_fa_field,
               check_momentum_balance, check_correction_velocity, check_eq5_fa,
-              check_advection, check_diagnostics, check_spread_radius, check_fa_discrete]
+              check_advection, check_diagnostics, check_spread_radius, check_fa_discrete,
+              check_symmetric_well]

@@ -40,10 +40,16 @@ MUTANTS = [
      "gsum[a] += L->w[i] * L->e[i][(a + 1) % L->dim] * v;"),
     ("lap_factor", "if (lap) lap[idx] = 2.0 * lsum / CS2;", "if (lap) lap[idx] = lsum / CS2;"),
     ("mirror_off_by_one", "if (c < 0) return -c - 1;", "if (c < 0) return -c;"),
-    ("dtheta_factor", "return 2.0 * beta * phi * (phi - 1.0) * (2.0 * phi - 1.0);",
-     "return 2.0 * beta * phi * (phi - 1.0) * (phi - 1.0);"),
-    ("mu_kappa_sign", "s->mu[idx] = dtheta(p->beta, s->phi[idx]) - p->kappa * s->lphi[idx];",
-     "s->mu[idx] = dtheta(p->beta, s->phi[idx]) + p->kappa * s->lphi[idx];"),
+    ("dtheta_factor", "return 2.0 * p->beta * phi * (phi - 1.0) * (2.0 * phi - 1.0);",
+     "return 2.0 * p->beta * phi * (phi - 1.0) * (phi - 1.0);"),
+    ("dtheta_sym_sign", "return 4.0 * p->beta * phi * (phi * phi - p->phi_star * p->phi_star);",
+     "return 4.0 * p->beta * phi * (phi * phi + p->phi_star * p->phi_star);"),
+    ("rho_sym_offset", "return p->rho_g + (phi + p->phi_star) / (2.0 * p->phi_star) * (p->rho_l - p->rho_g);",
+     "return p->rho_g + (phi + p->phi_star) / p->phi_star * (p->rho_l - p->rho_g);"),
+    ("beta_kappa_sym_power", "*beta = 3.0 * sigma / (4.0 * width * p2 * p2);",
+     "*beta = 3.0 * sigma / (4.0 * width * p2);"),
+    ("mu_kappa_sign", "s->mu[idx] = dtheta_well(p, s->phi[idx]) - p->kappa * s->lphi[idx];",
+     "s->mu[idx] = dtheta_well(p, s->phi[idx]) + p->kappa * s->lphi[idx];"),
     ("beta_kappa_swap", "*beta = 12.0 * sigma / width;", "*beta = 8.0 * sigma / width;"),
     ("gamma_no_half", "s->gamma = prm->theta_m / (prm->tau_f - 0.5);",
      "s->gamma = prm->theta_m / prm->tau_f;"),
@@ -51,22 +57,23 @@ MUTANTS = [
      "fsg[vert] += (s->rho[idx] - p->rho_ref) * p->gravity;"),
     ("surface_force_dropped", "fsg[k] = s->mu[idx] * s->gphi[k * n + idx];",
      "fsg[k] = 0.0 * s->gphi[k * n + idx];"),
-    ("correction_sign", "double c = sw * s->drho * p->theta_m * s->lmu[idx];",
-     "double c = -sw * s->drho * p->theta_m * s->lmu[idx];"),
-    ("correction_uses_lap_phi", "double c = sw * s->drho * p->theta_m * s->lmu[idx];",
-     "double c = sw * s->drho * p->theta_m * s->lphi[idx];"),
-    ("gradpsi_sign", "s->gpsi[k * n + idx] -= CS2 * s->drho * s->gphi[k * n + idx];",
-     "s->gpsi[k * n + idx] += CS2 * s->drho * s->gphi[k * n + idx];"),
+    ("correction_sign", "double c = sw * s->drho_dphi * p->theta_m * s->lmu[idx];",
+     "double c = -sw * s->drho_dphi * p->theta_m * s->lmu[idx];"),
+    ("correction_uses_lap_phi", "double c = sw * s->drho_dphi * p->theta_m * s->lmu[idx];",
+     "double c = sw * s->drho_dphi * p->theta_m * s->lphi[idx];"),
+    ("gradpsi_sign", "s->gpsi[k * n + idx] -= CS2 * s->drho_dphi * s->gphi[k * n + idx];",
+     "s->gpsi[k * n + idx] += CS2 * s->drho_dphi * s->gphi[k * n + idx];"),
     ("tau_no_half", "s->tau[idx] = 0.5 + nu / CS2;", "s->tau[idx] = nu / CS2;"),
     ("mu_gas_inverted", "s->mu_g = s->mu_l / prm->mu_ratio;", "s->mu_g = s->mu_l * prm->mu_ratio;"),
-    ("density_closure", "s->rho[idx] = p->rho_g + sum * s->drho;",
-     "s->rho[idx] = p->rho_l + sum * s->drho;"),
+    ("density_closure", "return p->rho_g + phi * (p->rho_l - p->rho_g);",
+     "return p->rho_l + phi * (p->rho_l - p->rho_g);"),
     ("collide_f_sign", "s->f[i * n + idx] = fi - (fi - fe[i]) / tf;",
      "s->f[i * n + idx] = fi + (fi - fe[i]) / tf;"),
     ("collide_g_no_trapezoid", "+ (1.0 - 1.0 / (2.0 * tg)) * src[i];", "+ src[i];"),
     ("stream_push", "s[a] = c[a] - L->e[i][a];", "s[a] = c[a] + L->e[i][a];"),
     ("bounce_back_same_dir", "int j = bb ? L->opp[i] : i;", "int j = i;"),
-    ("diag_weight", "double w = 2.0 * ph - 0.5;", "double w = 2.0 * ph - 1.0;"),
+    ("diag_weight", "double w = 2.0 * (ph - s->phi_g) / (s->phi_l - s->phi_g) - 0.5;",
+     "double w = 2.0 * (ph - s->phi_g) / (s->phi_l - s->phi_g) - 1.0;"),
 ]
 
 FAST_CHECKS = [c for c in P.ALL_CHECKS]

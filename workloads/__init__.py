@@ -49,16 +49,19 @@ class Case:
 
 def base_params(lattice, nx, ny, nz=1, wall=(0, 0, 0), *, sigma, width=4.0,
                 theta_m=0.1, tau_f=0.8, tau_g=0.8, rho_l=1.0, rho_g=0.1,
-                mu_ratio=None, gravity=0.0, rho_ref=None, remove_fa=0):
+                mu_ratio=None, gravity=0.0, rho_ref=None, remove_fa=0, well=0,
+                phi_star=0.5):
     """Physical parameters of a case.  mu_ratio defaults to the density ratio
-    (constant kinematic viscosity); rho_ref defaults to rho_g."""
+    (constant kinematic viscosity); rho_ref defaults to rho_g.  well = 0: the
+    double well of Eq. 1a with phi in [0, 1]; well = 1: the symmetric well of
+    Eq. 1b with phi in [-phi_star, phi_star]."""
     return dict(
         lattice=lattice, nx=int(nx), ny=int(ny), nz=int(nz), wall=[int(w) for w in wall],
         sigma=float(sigma), width=float(width), theta_m=float(theta_m),
         tau_f=float(tau_f), tau_g=float(tau_g), rho_l=float(rho_l), rho_g=float(rho_g),
         mu_ratio=float(rho_l / rho_g if mu_ratio is None else mu_ratio),
         gravity=float(gravity), rho_ref=float(rho_g if rho_ref is None else rho_ref),
-        remove_fa=int(remove_fa))
+        remove_fa=int(remove_fa), well=int(well), phi_star=float(phi_star))
 
 
 def _grid(nx, ny, nz):
@@ -97,6 +100,9 @@ def droplet_fields(params, centre, radius, *, film_height=None, impact_u=0.0,
         u += noise
     # Young-Laplace jump: sigma / R in 2-D, 2 sigma / R in 3-D.
     p = p_base + (dim - 1) * params["sigma"] / radius * phi_d
+    if params.get("well", 0):
+        # the symmetric well's order parameter: phi* tanh(2 d / W)
+        phi = params["phi_star"] * (2.0 * phi - 1.0)
     return phi, u, p
 
 
@@ -104,14 +110,14 @@ def droplet_fields(params, centre, radius, *, film_height=None, impact_u=0.0,
 
 def stationary_droplet(seed=0, n=128, radius=25.0, remove_fa=0, noise_amp=1e-4,
                        sigma=0.01, ratio=10.0, tau=0.8, theta_m=0.1, width=4.0,
-                       centre_jitter=2.0, name=None):
+                       centre_jitter=2.0, name=None, well=0, phi_star=0.5):
     """Stationary 2-D droplet in a periodic n x n box (128^2, R = 25, W = 4,
     ratio 10, sigma = 0.01, tau_f = tau_g = 0.8, theta_M = 0.1).
     Draws: centre jitter x, y ~ U(-2, 2); velocity noise N(0, 1e-4^2)."""
     rng = np.random.default_rng(seed)
     prm = base_params(D2Q9, n, n, sigma=sigma, width=width, theta_m=theta_m,
                       tau_f=tau, tau_g=tau, rho_l=1.0, rho_g=1.0 / ratio,
-                      remove_fa=remove_fa)
+                      remove_fa=remove_fa, well=well, phi_star=phi_star)
     jit = rng.uniform(-centre_jitter, centre_jitter, size=2) if centre_jitter else np.zeros(2)
     centre = (n / 2 + jit[0], n / 2 + jit[1])
     noise = rng.normal(0.0, noise_amp, size=(2, n * n)) if noise_amp else None

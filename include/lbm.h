@@ -58,6 +58,12 @@ enum { LBM_PERIODIC = 0, LBM_WALL = 1 };
  * f_0 is then rebuilt as phi - sum_{i>0} f_i from the stored values, so the
  * 16-bit rounding moves phi only between neighbours and sum phi is kept. */
 enum { LBM_FP32 = 0, LBM_FP16 = 1, LBM_BF16 = 2 };
+/* Double well of the free energy.  LBM_WELL_ASYMMETRIC (Eq. 1a):
+ * theta = beta phi^2 (phi - 1)^2, gas phi = 0, liquid phi = 1, density Eq. 4a.
+ * LBM_WELL_SYMMETRIC (Eq. 1b): theta = beta (phi^2 - phi*^2)^2, gas -phi*,
+ * liquid phi*, density Eq. 4b.  In both, rho and the dynamic viscosity are
+ * linear in phi between their gas and liquid values. */
+enum { LBM_WELL_ASYMMETRIC = 0, LBM_WELL_SYMMETRIC = 1 };
 
 /* Parameters of one case, in lattice units (dx = dt = 1). */
 typedef struct {
@@ -65,8 +71,9 @@ typedef struct {
   int32_t nx, ny, nz;        /* each >= 4; nz = 1 for D2Q9 */
   int32_t bc[3];             /* per axis LBM_PERIODIC or LBM_WALL (halfway bounce-back,
                                 mirror ghosts for the stencils: neutral wetting) */
-  double beta, kappa;        /* theta(phi) = beta phi^2 (phi-1)^2 and kappa (Eq. 1a);
-                                lbm_beta_kappa() converts sigma, W */
+  double beta, kappa;        /* beta of the double well (Eq. 1a or 1b, see well) and
+                                kappa; lbm_beta_kappa() / lbm_beta_kappa_sym()
+                                convert sigma, W */
   double theta_m;            /* mobility theta_M of Eq. 2 (> = 0) */
   double tau_f;              /* relaxation time of f (> 1/2); Gamma = theta_M/(tau_f-1/2) */
   double tau_g;              /* relaxation time of g in the liquid (> 1/2);
@@ -78,6 +85,9 @@ typedef struct {
   int32_t storage;           /* LBM_FP32 / LBM_FP16 / LBM_BF16 (same for all cases) */
   double p0;                 /* rest pressure of the 16-bit g deviations */
   double scale_f, scale_g;   /* powers of two for 16-bit storage; 0 = automatic */
+  int32_t well;              /* LBM_WELL_ASYMMETRIC (0, the zero-initialised default)
+                                or LBM_WELL_SYMMETRIC */
+  double phi_star;           /* phi* of the symmetric well (> 0); ignored otherwise */
 } lbm_case_params;
 
 /* FP64 diagnostics of one case at the current time level. */
@@ -87,7 +97,9 @@ typedef struct {
   double mass0;              /* sum phi at lbm_init */
   double mass_drift_rel;     /* |mass - mass0| / |mass0| */
   double momentum[3];        /* sum rho u */
-  double wsum;               /* sum w, w = clamp(2 phi - 1/2, 0, 1) */
+  double wsum;               /* sum w, w = clamp(2 s - 1/2, 0, 1) with s = (phi - phi_G) /
+                                (phi_L - phi_G) the fraction of the way from the
+                                gas to the liquid value of phi */
   double centroid[3];        /* sum w x / sum w (node coordinates) */
   double centroid_vel[3];    /* sum w u / sum w */
   double second_moment[3];   /* sum w (x - X)^2 / sum w per axis */
@@ -102,6 +114,13 @@ typedef struct lbm_handle lbm_handle;
  * with tension sigma (the paper states that beta and kappa set sigma and W,
  * without the formula). */
 int lbm_beta_kappa(double sigma, double width, double* beta, double* kappa);
+
+/* sigma, W, phi* -> beta = 3 sigma / (4 W phi*^4), kappa = 3 sigma W / (8 phi*^2):
+ * the pair for which phi* tanh(2 z / W) solves kappa phi'' = theta'(phi) for
+ * the symmetric well of Eq. 1b with tension sigma.  LBM_ERR_ARG for sigma < 0,
+ * W <= 0, phi* <= 0 or a NULL output. */
+int lbm_beta_kappa_sym(double sigma, double width, double phi_star, double* beta,
+                       double* kappa);
 
 /* Device bytes lbm_init needs for these cases (state ping-pong, field
  * scratch, reduction partials, tables).  Validates the parameters. */
@@ -129,7 +148,7 @@ int lbm_step(lbm_handle* h, int64_t nsteps);
 /* Macroscopic fields of case icase at the current time level, written to
  * caller-allocated host float arrays: phi[N], u[dim*N], p[N] (hydrodynamic
  * pressure), mu[N] (chemical potential), fa[dim*N] (the additional force
- * F_a = -u (rho_L - rho_G) theta_M lap mu of the current state, whichever
+ * F_a = -u (d rho / d phi) theta_M lap mu of the current state, whichever
  * model runs).  Any output may be NULL.  Synchronises the stream. */
 int lbm_moments(lbm_handle* h, int32_t icase, float* phi, float* u, float* p, float* mu,
                 float* fa);
@@ -155,7 +174,7 @@ int lbm_spread_radius(lbm_handle* h, int32_t icase, double level, double* radius
 /* The additional interfacial force F_a of Eq. 12 estimated from discrete
  * data rather than through Eq. 5:
  *   F_a = -u^n [ (rho^n - rho^(n-1)) + div(rho u)^n ],
- * rho = rho_G + phi (rho_L - rho_G) (Eq. 4a), the time derivative a backward
+ * rho linear in phi (Eq. 4a or 4b, by the case's well), the time derivative a backward
  * difference over one step, the divergence by the isotropic central scheme
  * with the step's periodic / mirror-ghost neighbours.  It tests the paper's
  * statement that d_t rho + div(rho u) is approximately Eq. 5.  phi_prev: device

@@ -37,6 +37,7 @@ class CaseParams(C.Structure):
         ("rho_g", C.c_double), ("mu_ratio", C.c_double), ("gravity", C.c_double),
         ("rho_ref", C.c_double), ("remove_fa", C.c_int32), ("storage", C.c_int32),
         ("p0", C.c_double), ("scale_f", C.c_double), ("scale_g", C.c_double),
+        ("well", C.c_int32), ("phi_star", C.c_double),
     ]
 
 
@@ -75,6 +76,7 @@ def lib():
     i32p = C.POINTER(C.c_int32)
     L.lbm_last_error.restype = C.c_char_p
     L.lbm_beta_kappa.argtypes = [C.c_double, C.c_double, dp, dp]
+    L.lbm_beta_kappa_sym.argtypes = [C.c_double, C.c_double, C.c_double, dp, dp]
     L.lbm_required_bytes.argtypes = [C.POINTER(CaseParams), C.c_int32, C.POINTER(C.c_size_t)]
     L.lbm_init.argtypes = [C.POINTER(CaseParams), C.c_int32, C.POINTER(dp), C.POINTER(dp),
                            C.POINTER(dp), _vp, C.c_size_t, _vp, C.c_int32, C.POINTER(_vp)]
@@ -125,15 +127,26 @@ def beta_kappa(sigma, width):
     return b.value, k.value
 
 
+def beta_kappa_sym(sigma, width, phi_star):
+    b, k = C.c_double(), C.c_double()
+    _check(lib().lbm_beta_kappa_sym(sigma, width, phi_star, C.byref(b), C.byref(k)))
+    return b.value, k.value
+
+
 def make_case(params, storage=FP32, p0=0.0, scale_f=0.0, scale_g=0.0):
-    """CaseParams from a parameter dict (sigma and width, or beta and kappa)."""
+    """CaseParams from a parameter dict (sigma and width, or beta and kappa;
+    well 0 = asymmetric, 1 = symmetric with phi_star)."""
     c = CaseParams()
     c.lattice = params["lattice"]
     c.nx, c.ny, c.nz = params["nx"], params["ny"], params.get("nz", 1)
     for a in range(3):
         c.bc[a] = params["wall"][a]
+    c.well = int(params.get("well", 0))
+    c.phi_star = float(params.get("phi_star", 0.5))
     if "beta" in params:
         c.beta, c.kappa = params["beta"], params["kappa"]
+    elif c.well:
+        c.beta, c.kappa = beta_kappa_sym(params["sigma"], params["width"], c.phi_star)
     else:
         c.beta, c.kappa = beta_kappa(params["sigma"], params["width"])
     for k in ("theta_m", "tau_f", "tau_g", "rho_l", "rho_g", "mu_ratio", "gravity", "rho_ref"):

@@ -212,7 +212,7 @@ k_fa_discrete(CaseDev c, const float* __restrict__ phi_prev, const float* __rest
     const int my = map_axis(y + ey, c.ny, c.wall_y);
     const int mz = DIM == 3 ? map_axis(z + ez, c.nz, c.wall_z) : 0;
     const unsigned j = mx + c.nx * (my + c.ny * mz);
-    const float rho = c.rho_g + phi[j] * c.drho;
+    const float rho = c.rho0 + phi[j] * c.drho;
     float eu = ex * f.u[0][j] + ey * f.u[1][j];
     if (DIM == 3) eu += ez * f.u[2][j];
     div += 3.0f * w * rho * eu;
@@ -282,8 +282,8 @@ k_diag_partial(CaseDev c, int dim, const float* __restrict__ phi, const float* _
     const int z = idx / (c.nx * c.ny);
     const double ph = phi[idx];
     const double u[3] = {ux[idx], uy[idx], dim == 3 ? (double)uz[idx] : 0.0};
-    const double rho = (double)c.rho_g + ph * (double)c.drho;
-    double w = 2.0 * ph - 0.5;
+    const double rho = (double)c.rho0 + ph * (double)c.drho;
+    double w = (double)c.wa * ph + (double)c.wb;
     w = w < 0.0 ? 0.0 : (w > 1.0 ? 1.0 : w);
     const double xc[3] = {(double)x, (double)y, (double)z};
     acc[DG_MASS] += ph;

@@ -26,15 +26,6 @@
 namespace lbm {
 namespace d2q9 {
 
-// theta'(phi) for theta = beta phi^2 (phi - 1)^2, with phi = hi + lo carried
-// as two floats: phi - 1 and 2 phi - 1 are formed before rounding to one
-// float, so they keep their absolute precision near phi = 1 and phi = 1/2.
-__device__ __forceinline__ float dtheta(const CaseDev& c, float hi, float lo) {
-  const float a = hi + lo;
-  const float b = (hi - 1.0f) + lo;
-  const float d = (2.0f * hi - 1.0f) + 2.0f * lo;
-  return c.beta2 * a * b * d;
-}
 
 // Differences of a float-float LDS field (hi, lo arrays, row pitch P):
 // hi differences of close values are exact, so the stencils below see phi to
@@ -88,7 +79,7 @@ __device__ __forceinline__ void grad_only(const float* s, int cx, int cy, float&
 __device__ __forceinline__ void recover(const CaseDev& c, float phi, float gx, float gy, float mu,
                                         float lmu, float m0, float m1x, float m1y, float& ux,
                                         float& uy, float& p) {
-  const float rho = c.rho_g + phi * c.drho;
+  const float rho = c.rho0 + phi * c.drho;
   const float fsx = mu * gx;
   const float fsy = mu * gy - (rho - c.rho_ref) * c.gravity;
   const float cc = c.corr * lmu;
@@ -552,7 +543,7 @@ __device__ __forceinline__ void tile_bcd(TileLds<TX, TY, RF>& L, const CaseDev& 
       fo.fax[idx] = -ux * c.fa_coef * lmu;
       fo.fay[idx] = -uy * c.fa_coef * lmu;
     } else {
-      const float rho = c.rho_g + ph * c.drho;
+      const float rho = c.rho0 + ph * c.drho;
       const float cc = c.corr * lmu;
       const float fx = mu * gx + cc * ux;
       const float fy = mu * gy - (rho - c.rho_ref) * c.gravity + cc * uy;
@@ -561,7 +552,7 @@ __device__ __forceinline__ void tile_bcd(TileLds<TX, TY, RF>& L, const CaseDev& 
       const float gpsx = gpx - (1.0f / 3.0f) * c.drho * gx;
       const float gpsy = gpy - (1.0f / 3.0f) * c.drho * gy;
       // tau = 1/2 + 3 nu, nu = mu_dyn(phi) / rho
-      const float mud = c.mu_g + ph * c.dmu;
+      const float mud = c.mu0 + ph * c.dmu;
       const float om = rho * __builtin_amdgcn_rcpf(0.5f * rho + 3.0f * mud);  // 1 / tau
       const float half = 1.0f - 0.5f * om;
       const float uu = ux * ux + uy * uy;
@@ -689,7 +680,7 @@ k_init(CaseDev c, int parity, const double* __restrict__ phi0, const double* __r
   const float ph = nh[0] + nl[0];
   const float ux = (float)u0[idx], uy = (float)u0[c.n + idx];
   const float p = (float)p0[idx];
-  const float rho = c.rho_g + ph * c.drho;
+  const float rho = c.rho0 + ph * c.drho;
   const float uu = ux * ux + uy * uy;
   char* dst = parity ? c.state[1] : c.state[0];
   float fsum = 0.0f;

@@ -16,13 +16,6 @@
 namespace lbm {
 namespace d3q19 {
 
-__device__ __forceinline__ float dtheta(const CaseDev& c, float hi, float lo) {
-  const float a = hi + lo;
-  const float b = (hi - 1.0f) + lo;
-  const float d = (2.0f * hi - 1.0f) + 2.0f * lo;
-  return c.beta2 * a * b * d;
-}
-
 __device__ __forceinline__ void coords(const CaseDev& c, unsigned idx, int& x, int& y, int& z) {
   x = idx % c.nx;
   const unsigned r = idx / c.nx;
@@ -244,7 +237,7 @@ k3_fields_t(CaseDev c, Fields3 fl, int want_lmu) {
     lmu = (1.0f / 3.0f) * la + (1.0f / 6.0f) * le;
   }
   const float ph = h0 + l0;
-  const float rho = c.rho_g + ph * c.drho;
+  const float rho = c.rho0 + ph * c.drho;
   // (rho - c/2) u = 3 sum e gbar + (F_s + G)/2, gravity along -z
   const float fsx = mu * g[0], fsy = mu * g[1];
   const float fsz = mu * g[2] - (rho - c.rho_ref) * c.gravity;
@@ -280,7 +273,7 @@ __device__ __forceinline__ void collide_node(const CaseDev& c, const OutPtrs<S, 
                                              const NodeFields& n) {
   const float ph = n.phh + n.phl;
   const float ux = n.ux, uy = n.uy, uz = n.uz, p = n.p, mu = n.mu;
-  const float rho = c.rho_g + ph * c.drho;
+  const float rho = c.rho0 + ph * c.drho;
   const float cc = c.corr * n.lmu;
   const float fx = mu * n.gx + cc * ux;
   const float fy = mu * n.gy + cc * uy;
@@ -288,7 +281,7 @@ __device__ __forceinline__ void collide_node(const CaseDev& c, const OutPtrs<S, 
   const float gpsx = n.gpx - (1.0f / 3.0f) * c.drho * n.gx;
   const float gpsy = n.gpy - (1.0f / 3.0f) * c.drho * n.gy;
   const float gpsz = n.gpz - (1.0f / 3.0f) * c.drho * n.gz;
-  const float mud = c.mu_g + ph * c.dmu;
+  const float mud = c.mu0 + ph * c.dmu;
   const float om = rho * __builtin_amdgcn_rcpf(0.5f * rho + 3.0f * mud);  // 1 / tau
   const float half = 1.0f - 0.5f * om;
   const float uu = ux * ux + uy * uy + uz * uz;
@@ -414,7 +407,7 @@ k3_init(CaseDev c, int parity, const double* __restrict__ phi0, const double* __
   const unsigned n = c.n;
   const float ux = (float)u0[idx], uy = (float)u0[n + idx], uz = (float)u0[2 * n + idx];
   const float p = (float)p0[idx];
-  const float rho = c.rho_g + ph * c.drho;
+  const float rho = c.rho0 + ph * c.drho;
   const float uu = ux * ux + uy * uy + uz * uz;
   char* dst = parity ? c.state[1] : c.state[0];
   float fsum = 0.0f;

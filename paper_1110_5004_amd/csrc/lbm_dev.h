@@ -23,12 +23,20 @@ struct CaseDev {
                     // so every byte offset into it fits 32 bits
   char* state[2];   // the two copies of the stored populations
   // physics (float)
-  float beta2;      // 2 beta            (theta'(phi) = 2 beta phi (phi-1)(2 phi-1))
+  // theta'(phi) = th_k phi (phi - th_r1) (phi - th_r2): the asymmetric well
+  // beta phi^2 (phi-1)^2 has th_k = 4 beta, roots 1 and 1/2; the symmetric
+  // well beta (phi^2 - phi*^2)^2 has th_k = 4 beta, roots phi* and -phi*
+  float th_k, th_r1, th_r2;
   float kappa;
   float gamma3;     // 3 Gamma, Gamma = theta_M / (tau_f - 1/2)
   float omega_f;    // 1 / tau_f
-  float rho_g, drho;
-  float mu_g, dmu;  // dynamic viscosity mu_G and mu_L - mu_G
+  float rho0, drho; // rho = rho0 + drho phi (Eq. 4a: rho_G, rho_L - rho_G;
+                    // Eq. 4b: (rho_L + rho_G) / 2, (rho_L - rho_G) / (2 phi*))
+  float mu0, dmu;   // dynamic viscosity mu0 + dmu phi, mu_G at the gas value
+                    // of phi and mu_L at the liquid value
+  float wa, wb;     // diagnostic weight w = wa phi + wb before clamping to [0, 1]:
+                    // 0, 1/2, 1 at a quarter, half, three quarters of the way
+                    // from the gas to the liquid value of phi
   float gravity, rho_ref;
   float corr;       // remove_fa * drho * theta_M  (coefficient of lap mu in -F_a / u)
   float fa_coef;    // drho * theta_M           (F_a dump, whichever model runs)
@@ -36,6 +44,17 @@ struct CaseDev {
   float scale_f, inv_scale_f, scale_g, inv_scale_g;
   int pad1;
 };
+
+// theta'(phi) of the double well (Eq. 1a / 1b), with phi = hi + lo carried as
+// two floats: phi - th_r1 and phi - th_r2 are formed before rounding to one
+// float, so they keep their absolute precision near the roots (the bulk values
+// of phi and the interface midpoint).
+__device__ __forceinline__ float dtheta(const CaseDev& c, float hi, float lo) {
+  const float a = hi + lo;
+  const float b = (hi - c.th_r1) + lo;
+  const float d = (hi - c.th_r2) + lo;
+  return c.th_k * a * b * d;
+}
 
 // Per-tile work item: case index and tile origin.
 struct TileDev {

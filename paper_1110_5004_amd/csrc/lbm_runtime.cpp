@@ -92,6 +92,10 @@ int validate(const lbm_case_params* cs, int32_t n) {
       return fail(LBM_ERR_ARG, "case %d: theta_m, beta, kappa must be >= 0", k);
     if (c.remove_fa != 0 && c.remove_fa != 1)
       return fail(LBM_ERR_ARG, "case %d: remove_fa must be 0 or 1", k);
+    if (c.well != LBM_WELL_ASYMMETRIC && c.well != LBM_WELL_SYMMETRIC)
+      return fail(LBM_ERR_ARG, "case %d: well must be LBM_WELL_ASYMMETRIC or LBM_WELL_SYMMETRIC", k);
+    if (c.well == LBM_WELL_SYMMETRIC && !(c.phi_star > 0.0 && std::isfinite(c.phi_star)))
+      return fail(LBM_ERR_ARG, "case %d: phi_star must be finite and > 0", k);
     if ((c.scale_f != 0.0 && !is_pow2(c.scale_f)) || (c.scale_g != 0.0 && !is_pow2(c.scale_g)))
       return fail(LBM_ERR_ARG, "case %d: 16-bit scales must be powers of two (or 0)", k);
   }
@@ -247,18 +251,29 @@ CaseDev derive(const lbm_case_params& p, char* s0, char* s1) {
   c.stride = (unsigned)stride_of(p);
   c.state[0] = s0;
   c.state[1] = s1;
-  const double drho = p.rho_l - p.rho_g;
+  // bulk values of phi: 0 and 1 for the asymmetric well, -phi* and phi* for
+  // the symmetric one; rho and the dynamic viscosity are linear in phi
+  // between the gas and the liquid value (Eq. 4a / 4b)
+  const bool sym = p.well == LBM_WELL_SYMMETRIC;
+  const double phi_g = sym ? -p.phi_star : 0.0;
+  const double phi_l = sym ? p.phi_star : 1.0;
+  const double drho = (p.rho_l - p.rho_g) / (phi_l - phi_g);  // d rho / d phi
   const double gamma = p.theta_m / (p.tau_f - 0.5);  // theta_M = Gamma (tau_f - 1/2)
   const double mu_l = p.rho_l * (p.tau_g - 0.5) / 3.0;  // nu_L = cs^2 (tau_g - 1/2)
   const double mu_g = mu_l / p.mu_ratio;
-  c.beta2 = (float)(2.0 * p.beta);
+  const double dmu = (mu_l - mu_g) / (phi_l - phi_g);
+  c.th_k = (float)(4.0 * p.beta);
+  c.th_r1 = (float)phi_l;
+  c.th_r2 = (float)(sym ? phi_g : 0.5);
   c.kappa = (float)p.kappa;
   c.gamma3 = (float)(3.0 * gamma);
   c.omega_f = (float)(1.0 / p.tau_f);
-  c.rho_g = (float)p.rho_g;
+  c.rho0 = (float)(p.rho_g - phi_g * drho);
   c.drho = (float)drho;
-  c.mu_g = (float)mu_g;
-  c.dmu = (float)(mu_l - mu_g);
+  c.mu0 = (float)(mu_g - phi_g * dmu);
+  c.dmu = (float)dmu;
+  c.wa = (float)(2.0 / (phi_l - phi_g));
+  c.wb = (float)(-2.0 * phi_g / (phi_l - phi_g) - 0.5);
   c.gravity = (float)p.gravity;
   c.rho_ref = (float)p.rho_ref;
   c.corr = (float)(p.remove_fa ? drho * p.theta_m : 0.0);
@@ -420,6 +435,16 @@ int lbm_beta_kappa(double sigma, double width, double* beta, double* kappa) {
     return fail(LBM_ERR_ARG, "need sigma >= 0, W > 0 and output pointers");
   *beta = 12.0 * sigma / width;
   *kappa = 1.5 * sigma * width;
+  return LBM_OK;
+}
+
+int lbm_beta_kappa_sym(double sigma, double width, double phi_star, double* beta,
+                       double* kappa) {
+  if (!beta || !kappa || !(width > 0.0) || !(sigma >= 0.0) || !(phi_star > 0.0))
+    return fail(LBM_ERR_ARG, "need sigma >= 0, W > 0, phi_star > 0 and output pointers");
+  const double p2 = phi_star * phi_star;
+  *beta = 3.0 * sigma / (4.0 * width * p2 * p2);
+  *kappa = 3.0 * sigma * width / (8.0 * p2);
   return LBM_OK;
 }
 

@@ -27,6 +27,18 @@ def test_beta_kappa(L):
         B.beta_kappa(0.01, 0.0)
 
 
+def test_beta_kappa_sym(L):
+    # phi* = 1: beta = 3 sigma / (4 W), kappa = 3 sigma W / 8
+    b, k = B.beta_kappa_sym(0.01, 4.0, 1.0)
+    assert abs(b - 0.001875) < 1e-16 and abs(k - 0.015) < 1e-16
+    # phi* = 1/2 maps phi in [-1/2, 1/2] onto the asymmetric well's [0, 1]:
+    # same beta and kappa
+    assert B.beta_kappa_sym(0.01, 4.0, 0.5) == pytest.approx(B.beta_kappa(0.01, 4.0), rel=1e-15)
+    for bad in ((0.01, 4.0, 0.0), (0.01, 0.0, 1.0), (-1.0, 4.0, 1.0)):
+        with pytest.raises(B.LbmError):
+            B.beta_kappa_sym(*bad)
+
+
 def _params(**kw):
     p = dict(lattice=0, nx=16, ny=16, nz=1, wall=[0, 0, 0], sigma=0.01, width=4.0,
              theta_m=0.1, tau_f=0.8, tau_g=0.8, rho_l=1.0, rho_g=0.1, mu_ratio=10.0,
@@ -38,7 +50,9 @@ def _params(**kw):
 @pytest.mark.parametrize("bad", [dict(tau_f=0.5), dict(tau_g=0.3), dict(rho_g=0.0),
                                  dict(nx=3), dict(nz=2), dict(remove_fa=2),
                                  dict(wall=[0, 2, 0]), dict(mu_ratio=-1.0),
-                                 dict(theta_m=float("nan"))])
+                                 dict(theta_m=float("nan")), dict(well=2),
+                                 dict(well=1, phi_star=0.0, beta=0.01, kappa=0.01),
+                                 dict(well=1, phi_star=float("inf"), beta=0.01, kappa=0.01)])
 def test_invalid_parameters_rejected(L, bad):
     c = B.make_case(_params(**bad))
     nbytes = C.c_size_t()

@@ -28,7 +28,10 @@ def build(extra_flags=(), out=LIB, verbose=False):
 
 
 def ensure_built():
-    if not os.path.exists(LIB):
+    """Build when the library is missing or older than a source or header."""
+    deps = SOURCES + [os.path.join(HERE, "lbm_oracle.h")]
+    if (not os.path.exists(LIB) or
+            os.path.getmtime(LIB) < max(os.path.getmtime(d) for d in deps)):
         build()
     return LIB
 

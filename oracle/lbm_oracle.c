@@ -11,6 +11,8 @@
  *   additional force F_a = -u [d_t rho + div(rho u)] .... Eq. 12, evaluated
  *                                 with Eq. 5 as -u (drho) theta_M lap mu
  *   corrected model: -F_a added to the forcing term ...... paragraph after Eq. 12
+ *   symmetric well and its density law .................. Eq. 1b, Eq. 4b
+ *   F_a from discrete data; F_a in Lee and Lin's form .... Eq. 12; Eq. 11
  *   isotropic central first derivatives and Laplacian .... splash-test paragraph
  * The order-parameter equation of the cited original model is not printed in
  * the paper; it is read as the plain BGK Cahn-Hilliard LBE whose equilibrium
@@ -194,6 +196,16 @@ void orc_grad_lap(const orc_params* prm, const double* field, double* grad,
 static double dtheta_well(const orc_params* p, double phi) {
   if (p->well) return 4.0 * p->beta * phi * (phi * phi - p->phi_star * p->phi_star);
   return 2.0 * p->beta * phi * (phi - 1.0) * (2.0 * phi - 1.0);
+}
+
+/* theta(phi) itself: beta phi^2 (phi - 1)^2 (Eq. 1a) or beta (phi^2 - phi*^2)^2
+ * (Eq. 1b). */
+static double theta_well(const orc_params* p, double phi) {
+  if (p->well) {
+    const double d = phi * phi - p->phi_star * p->phi_star;
+    return p->beta * d * d;
+  }
+  return p->beta * phi * phi * (phi - 1.0) * (phi - 1.0);
 }
 
 /* Density from the order parameter: Eq. 4a, rho_G + phi (rho_L - rho_G), or
@@ -661,6 +673,43 @@ void orc_fa_discrete(const orc_params* prm, const double* phi_prev, const double
   free(m);
   free(grad);
   free(div);
+}
+
+void orc_fa_leelin(const orc_params* prm, const double* phi, const double* u,
+                   const double* pr, double* out) {
+  lat_t L;
+  if (lat_fill(prm->lattice, &L)) return;
+  const long n = count_nodes(prm);
+  const double phi_g = prm->well ? -prm->phi_star : 0.0;
+  const double phi_l = prm->well ? prm->phi_star : 1.0;
+  /* dynamic viscosity: mu_L = rho_L nu_L with nu_L = cs^2 (tau_g - 1/2),
+   * mu_G = mu_L / ratio, linear in phi between the bulk values */
+  const double mu_l = prm->rho_l * CS2 * (prm->tau_g - 0.5);
+  const double mu_g = mu_l / prm->mu_ratio;
+  double* q = alloc0(n);
+  double* lam = alloc0(n);
+  double* gq = alloc0((long)L.dim * n);
+  double* lq = alloc0(n);
+  double* gl = alloc0((long)L.dim * n);
+  for (long idx = 0; idx < n; ++idx) {
+    const double ph = phi[idx];
+    const double thermo = ph * dtheta_well(prm, ph) - theta_well(prm, ph);  /* P */
+    q[idx] = thermo - pr[idx];
+    const double mud = mu_g + (ph - phi_g) / (phi_l - phi_g) * (mu_l - mu_g);
+    lam[idx] = mud / (rho_of(prm, ph) * CS2);
+  }
+  grad_lap_lat(prm, &L, q, gq, lq);
+  grad_lap_lat(prm, &L, lam, gl, NULL);
+  for (long idx = 0; idx < n; ++idx) {
+    double div = lam[idx] * lq[idx];
+    for (int a = 0; a < L.dim; ++a) div += gl[a * n + idx] * gq[a * n + idx];
+    for (int a = 0; a < L.dim; ++a) out[a * n + idx] = -u[a * n + idx] * div;
+  }
+  free(q);
+  free(lam);
+  free(gq);
+  free(lq);
+  free(gl);
 }
 
 void orc_get_state(const orc_sim* s, double* f, double* g) {

@@ -105,11 +105,25 @@ double orc_spread_radius(int nx, int ny, int nz, const double* phi, double level
  *   F_a = -u [ (rho^n - rho^(n-1)) + div(rho u)^n ],
  * the time derivative a backward difference over one step, the divergence by
  * the isotropic central scheme (sum over components of the gradient of the
- * component, with periodic wrap or mirror ghosts), rho = rho_G +
- * phi (rho_L - rho_G) (Eq. 4a).  phi_prev, phi: N values at n-1 and n; u: dim*N
+ * component, with periodic wrap or mirror ghosts), rho linear in phi
+ * (Eq. 4a or 4b).  phi_prev, phi: N values at n-1 and n; u: dim*N
  * (SoA) at n; out: dim*N (SoA). */
 void orc_fa_discrete(const orc_params* prm, const double* phi_prev, const double* phi,
                      const double* u, double* out);
+
+/* The additional force of Eq. 12 in the form it takes for Lee and Lin's model,
+ * where d_t rho + div(rho u) is given by Eq. 11:
+ *   F_a = -u div[ lambda (grad P - grad p) ],
+ * lambda = mu / (rho cs^2) with mu the dynamic viscosity (the only reading
+ * for which lambda has the dimension of a time: mu_L = rho_L cs^2 (tau_g -
+ * 1/2), mu_G = mu_L / ratio, linear in phi between the bulk values), P the
+ * thermodynamic pressure read as the equation of state of the free energy of
+ * Eq. 1, P = phi theta'(phi) - theta(phi), and p the hydrodynamic pressure.
+ * The divergence is expanded as lambda lap(P - p) + grad lambda . grad(P - p),
+ * each operator the isotropic central scheme.  phi, p: N values; u: dim*N
+ * (SoA); out: dim*N (SoA). */
+void orc_fa_leelin(const orc_params* prm, const double* phi, const double* u,
+                   const double* pr, double* out);
 
 /* Raw pre-collision populations f[Q*N], g[Q*N] (plane i at offset i*N). */
 void orc_get_state(const orc_sim* s, double* f, double* g);

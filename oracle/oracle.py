@@ -62,6 +62,7 @@ def load(path=None):
     lib.orc_stream_words.argtypes = [P, _UP, _UP]
     lib.orc_spread_radius.argtypes = [C.c_int, C.c_int, C.c_int, _DP, C.c_double]
     lib.orc_fa_discrete.argtypes = [P, _DP, _DP, _DP, _DP]
+    lib.orc_fa_leelin.argtypes = [P, _DP, _DP, _DP, _DP]
     lib.orc_spread_radius.restype = C.c_double
     if path is None:
         _lib = lib
@@ -104,6 +105,20 @@ def fa_discrete(case, phi_prev, phi, u, lib=None):
     lib.orc_fa_discrete(C.byref(prm), np.ascontiguousarray(phi_prev, dtype=np.float64).ravel(),
                         np.ascontiguousarray(phi, dtype=np.float64).ravel(),
                         np.ascontiguousarray(u, dtype=np.float64).ravel(), out)
+    return out.reshape(dim, n)
+
+
+def fa_leelin(case, phi, u, p, lib=None):
+    """F_a of Eq. 12 in Lee and Lin's form (Eq. 11): -u div[lambda (grad P -
+    grad p)] (see orc_fa_leelin).  Returns (dim, N)."""
+    lib = lib or load()
+    prm = make_params(case, lib)
+    n = int(np.asarray(phi).size)
+    dim = 2 if case["lattice"] == D2Q9 else 3
+    out = np.zeros(dim * n)
+    lib.orc_fa_leelin(C.byref(prm), np.ascontiguousarray(phi, dtype=np.float64).ravel(),
+                      np.ascontiguousarray(u, dtype=np.float64).ravel(),
+                      np.ascontiguousarray(p, dtype=np.float64).ravel(), out)
     return out.reshape(dim, n)
 
 

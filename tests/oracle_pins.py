@@ -696,6 +696,80 @@ def check_fa_discrete(lib):
     assert np.abs(f).max() < 1e-17
 
 
+def check_fa_leelin(lib):
+    """F_a in Lee and Lin's form, -u div[lambda (grad P - grad p)], against
+    closed forms of x-only fields, for which the isotropic D2Q9 and D3Q19
+    stencils reduce to the central difference (g(x+1) - g(x-1)) / 2 and the
+    three-point second difference g(x+1) + g(x-1) - 2 g(x):
+    (a) at rest it is 0;  (b) in a uniform bulk (P = 0 at both minima) with
+    p = b sin(kx) it is -u lambda 4 b sin^2(k/2) sin(kx), lambda = tau_g - 1/2
+    in the liquid and (tau_g - 1/2) (rho_L / rho_G) / ratio in the gas;
+    (c) for phi = c + a sin(kx), p = b cos(kx) it is -u [lambda lap q +
+    grad lambda . grad q] with the closed forms P = beta phi^2 (phi - 1)
+    (3 phi - 1) (Eq. 1a) or beta (phi^2 - phi*^2)(3 phi^2 + phi*^2) (Eq. 1b)
+    and lambda = 3 mu_dyn(phi) / rho(phi);  (d) a y-only field gives no
+    x-force when u is along x only through the divergence's y part."""
+    nx, ny = 48, 6
+    k = 2 * math.pi * 2 / nx
+    for lat, nz in ((W.D2Q9, 1), (W.D3Q19, 4)):
+        n = nx * ny * nz
+        x = np.tile(np.arange(nx, dtype=float), ny * nz)
+        dim = 2 if lat == W.D2Q9 else 3
+        U = np.zeros((dim, n))
+        U[0], U[1] = 0.03, -0.02
+        for well, ps, (c0, c1) in ((0, 0.5, (0.0, 1.0)), (1, 0.8, (-0.8, 0.8))):
+            case = _case(nx, ny, nz=nz, lattice=lat, well=well, phi_star=ps, mu_ratio=4.0,
+                         tau_g=0.7)
+            beta, _ = (O.beta_kappa_sym(0.01, 4.0, ps, lib) if well
+                       else O.beta_kappa(0.01, 4.0, lib))
+            mu_l = 1.0 * (0.7 - 0.5) / 3.0
+            mu_g = mu_l / 4.0
+
+            def lam_of(ph):
+                frac = (ph - c0) / (c1 - c0)
+                return 3.0 * (mu_g + frac * (mu_l - mu_g)) / (0.1 + frac * 0.9)
+
+            def p_of(ph):
+                if well:
+                    return beta * (ph * ph - ps * ps) * (3 * ph * ph + ps * ps)
+                return beta * ph * ph * (ph - 1.0) * (3 * ph - 1.0)
+
+            # (a)
+            phi = c0 + (c1 - c0) * (0.5 + 0.2 * np.sin(k * x))
+            assert np.abs(O.fa_leelin(case, phi, np.zeros((dim, n)), np.zeros(n), lib)).max() == 0
+            # (b) both bulks
+            b = 3e-4
+            for bulk, lam in ((c1, 0.2), (c0, 0.2 * 10.0 / 4.0)):
+                f = O.fa_leelin(case, np.full(n, bulk), U, b * np.sin(k * x), lib)
+                want = -U * lam * 4 * b * math.sin(k / 2) ** 2 * np.sin(k * x)
+                assert np.allclose(f, want, rtol=1e-12, atol=1e-18), (lat, well, bulk)
+            # (c)
+            phi = 0.5 * (c0 + c1) + 0.3 * (c1 - c0) * np.sin(k * x)
+            pr = b * np.cos(k * x)
+            f = O.fa_leelin(case, phi, U, pr, lib)
+            q = p_of(phi) - pr
+            lam = lam_of(phi)
+
+            def sh(g, d):
+                return np.roll(g.reshape(-1, nx), -d, axis=1).ravel()   # g(x + d)
+
+            div = lam * (sh(q, 1) + sh(q, -1) - 2 * q) + \
+                0.25 * (sh(lam, 1) - sh(lam, -1)) * (sh(q, 1) - sh(q, -1))
+            assert np.allclose(f, -U * div, rtol=1e-10, atol=1e-20), (lat, well)
+            assert np.abs(div).max() > 1e-5
+    # (d) y-only field: the divergence is along y only, F_a is still -u times it
+    case = _case(8, 32)
+    y = np.repeat(np.arange(32, dtype=float), 8)
+    phi = 0.5 + 0.3 * np.sin(2 * math.pi * y / 32)
+    Ux = np.vstack([np.full(256, 0.01), np.zeros(256)])
+    f = O.fa_leelin(case, phi, Ux, np.zeros(256), lib)
+    assert np.abs(f[1]).max() == 0.0 and np.abs(f[0]).max() > 0.0
+    fx = O.fa_leelin(_case(32, 8), np.tile(0.5 + 0.3 * np.sin(2 * math.pi *
+                                                             np.arange(32.0) / 32), 8),
+                     Ux, np.zeros(256), lib)
+    assert np.allclose(np.sort(fx[0]), np.sort(f[0]), rtol=1e-12, atol=1e-20)
+
+
 def check_symmetric_well(lib):
     """The symmetric well of Eq. 1b, theta = beta (phi^2 - phi*^2)^2, with the
     density law of Eq. 4b, rho = rho_G + (phi + phi*) / (2 phi*) (rho_L - rho_G):
@@ -754,4 +828,4 @@ ALL_CHECKS = [check_lattice, check_feq_moments, check_geq_moments, check_source_
               check_shear_wave, check_ch_diffusion, check_switch_noop, check_fa_field,
               check_momentum_balance, check_correction_velocity, check_eq5_fa,
               check_advection, check_diagnostics, check_spread_radius, check_fa_discrete,
-              check_symmetric_well]
+              check_symmetric_well, check_fa_leelin]

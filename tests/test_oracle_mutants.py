@@ -74,6 +74,16 @@ MUTANTS = [
     ("bounce_back_same_dir", "int j = bb ? L->opp[i] : i;", "int j = i;"),
     ("diag_weight", "double w = 2.0 * (ph - s->phi_g) / (s->phi_l - s->phi_g) - 0.5;",
      "double w = 2.0 * (ph - s->phi_g) / (s->phi_l - s->phi_g) - 1.0;"),
+    ("leelin_thermo_sign", "ph * dtheta_well(prm, ph) - theta_well(prm, ph);",
+     "ph * dtheta_well(prm, ph) + theta_well(prm, ph);"),
+    ("leelin_no_grad_lambda", "div += gl[a * n + idx] * gq[a * n + idx];",
+     "div += 0.0 * gl[a * n + idx] * gq[a * n + idx];"),
+    ("leelin_lambda_liquid_rho", "lam[idx] = mud / (rho_of(prm, ph) * CS2);",
+     "lam[idx] = mud / (prm->rho_l * CS2);"),
+    ("leelin_visc_reversed", "const double mud = mu_g + (ph - phi_g) / (phi_l - phi_g) * (mu_l - mu_g);",
+     "const double mud = mu_g + (phi_l - ph) / (phi_l - phi_g) * (mu_l - mu_g);"),
+    ("theta_asym_power", "return p->beta * phi * phi * (phi - 1.0) * (phi - 1.0);",
+     "return p->beta * phi * phi * (phi - 1.0);"),
 ]
 
 FAST_CHECKS = [c for c in P.ALL_CHECKS]

@@ -39,9 +39,10 @@ def parse():
     ap.add_argument("--no-extra", action="store_true", help="skip the FP16 / original-model legs")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--workload", default="splash1024x512",
-                    choices=["splash1024x512", "droplet4096", "splash3d"],
+                    choices=["splash1024x512", "droplet4096", "splash3d", "fa_diagnostics"],
                     help="splash1024x512 (the benchmark), droplet4096 (profiling of "
-                         "the HBM-bound regime) or splash3d (the D3Q19 step alone)")
+                         "the HBM-bound regime), splash3d (the D3Q19 step alone) or "
+                         "fa_diagnostics (the two F_a diagnostics alone)")
     ap.add_argument("--variant", type=int, default=-1,
                     help="tile variant; -1 = autotuned")
     return ap.parse_args()
@@ -178,6 +179,52 @@ def leg_paper(torch, W, hip):
     return out
 
 
+# Algorithmic bytes per node of the F_a diagnostic kernels (2-D, FP32 fields):
+# phi (or phi and phi^(n-1)), u, and p read once, F_a written: 4 + 4 + 8 + 8.
+FA_DIAG_BYTES = 24
+
+
+def leg_fa_diagnostics(torch, W, hip, reps=20):
+    """The two F_a diagnostics (from discrete data, and in Lee and Lin's form)
+    on the 4096^2 droplet, FP32, corrected model: each call dumps the fields
+    (the same dump lbm_moments_device makes) and runs one node-parallel
+    kernel.  The kernel's own time is the call minus the dump alone, priced
+    at its algorithmic bytes (FA_DIAG_BYTES per node)."""
+    case = W.big_droplet(remove_fa=1)
+    sim = hip.Simulation([case])
+    sim.step(20)
+    prev = sim.moments_device()["phi"].clone()
+    sim.step(1)
+    n = case.n
+    stream = torch.cuda.current_stream()
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / 1e3 / reps
+
+    t_dump = timed(lambda: sim.moments_device())
+    t_ll = timed(lambda: sim.fa_leelin())
+    t_fd = timed(lambda: sim.fa_discrete(prev))
+    finite = bool(torch.isfinite(sim.fa_leelin()).all()) and \
+        bool(torch.isfinite(sim.fa_discrete(prev)).all())
+    sim.close()
+    out = dict(workload="droplet4096", nodes=n, dump_us=round(t_dump * 1e6, 1), finite=finite)
+    for name, t in (("fa_leelin", t_ll), ("fa_discrete", t_fd)):
+        k = max(t - t_dump, 1e-9)
+        gbs = FA_DIAG_BYTES * n / k / 1e9
+        out[name] = dict(call_us=round(t * 1e6, 1), kernel_us=round(k * 1e6, 1),
+                         achieved_gbs=round(gbs, 1), frac=round(gbs / HBM_PEAK_GBS, 4))
+    return out
+
+
 def pull_copy_ceiling(torch, hip, lattice, storage, dims, reps=200):
     """Seconds per launch of the pull-copy calibration kernel: the step's
     reads (every population from x - e_i) and writes in the same plane
@@ -287,6 +334,9 @@ def main():
     if a.workload == "splash3d":
         main_3d(a, torch, W, hip)
         return
+    if a.workload == "fa_diagnostics":
+        print(json.dumps({"fa_diagnostics": leg_fa_diagnostics(torch, W, hip)}), flush=True)
+        return
 
     main_leg = leg(torch, W, hip, a.storage, a.remove_fa, a.steps, a.warmup, a.workload,
                    a.variant)
@@ -342,6 +392,7 @@ def main():
                                           for st, rf in (("fp16", 1), ("fp16", 0), ("fp32", 1))}
         out["ensemble64"] = {st: leg_ensemble(torch, W, hip, st) for st in ("fp32", "fp16")}
         out["paper_experiments"] = leg_paper(torch, W, hip)
+        out["fa_diagnostics"] = leg_fa_diagnostics(torch, W, hip)
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(W, a.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -183,6 +183,24 @@ int lbm_spread_radius(lbm_handle* h, int32_t icase, double level, double* radius
  * caller-owned; enqueued on the handle's stream (no synchronization). */
 int lbm_fa_discrete(lbm_handle* h, int32_t icase, const float* phi_prev, float* fa);
 
+/* The additional force of Eq. 12 in the form it takes for Lee and Lin's
+ * model, where d_t rho + div(rho u) is given by Eq. 11:
+ *   F_a = -u div[ lambda (grad P - grad p) ]
+ * evaluated on the current fields of case icase (whichever model runs):
+ *   lambda = mu / (rho cs^2), mu the dynamic viscosity (linear in phi between
+ *            mu_G and mu_L; the reading under which lambda is a time);
+ *   P      = phi theta'(phi) - theta(phi), the equation of state of the
+ *            free energy of Eq. 1 (the case's well);
+ *   p      = the hydrodynamic pressure of the step;
+ *   div[lambda grad q] = lambda lap q + grad lambda . grad q, each operator the
+ *   isotropic central scheme with the step's periodic / mirror-ghost
+ *   neighbours.
+ * It is a diagnostic: it compares the Lee-Lin density source with the Eq. 5
+ * one on the same flow.  fa: device float[dim*N] (SoA), caller-owned, written.
+ * Enqueued on the handle's stream (no synchronization).  LBM_ERR_ARG for a
+ * NULL handle or output or a bad case index. */
+int lbm_fa_leelin(lbm_handle* h, int32_t icase, float* fa);
+
 /* Number of cases, time level, and bytes of one case's raw state. */
 int lbm_info(const lbm_handle* h, int32_t* ncases, int64_t* step, int32_t* storage);
 int lbm_state_bytes(const lbm_handle* h, int32_t icase, size_t* bytes);

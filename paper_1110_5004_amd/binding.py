@@ -86,6 +86,7 @@ def lib():
     L.lbm_diagnostics.argtypes = [_vp, C.c_int32, C.POINTER(Diag)]
     L.lbm_spread_radius.argtypes = [_vp, C.c_int32, C.c_double, C.POINTER(C.c_double)]
     L.lbm_fa_discrete.argtypes = [_vp, C.c_int32, _vp, _vp]
+    L.lbm_fa_leelin.argtypes = [_vp, C.c_int32, _vp]
     L.lbm_info.argtypes = [_vp, i32p, C.POINTER(C.c_int64), i32p]
     L.lbm_state_bytes.argtypes = [_vp, C.c_int32, C.POINTER(C.c_size_t)]
     L.lbm_get_state.argtypes = [_vp, C.c_int32, _vp, C.c_size_t]
@@ -281,9 +282,22 @@ class Simulation:
                                      C.c_void_p(out.data_ptr())))
         return out.view(self.dim, n)
 
-    def spread_radius(self, icase=0, level=0.5):
+    def fa_leelin(self, icase=0):
+        """F_a in Lee and Lin's form (see lbm_fa_leelin) on the current
+        fields; returns a (dim, N) device tensor."""
+        t = self.torch
+        n = self.n_nodes(icase)
+        out = t.empty(self.dim * n, dtype=t.float32, device=self.device)
+        _check(lib().lbm_fa_leelin(self.h, icase, C.c_void_p(out.data_ptr())))
+        return out.view(self.dim, n)
+
+    def spread_radius(self, icase=0, level=None):
         """Largest half-distance between the outermost phi = level crossings
-        of a grid row in x (the droplet half-width of the paper's Fig. 5)."""
+        of a grid row in x (the droplet half-width of the paper's Fig. 5);
+        level defaults to the interface midpoint of the case's well (1/2, or
+        0 for the symmetric well)."""
+        if level is None:
+            level = 0.0 if self.params[icase].get("well", 0) else 0.5
         r = C.c_double()
         _check(lib().lbm_spread_radius(self.h, icase, float(level), C.byref(r)))
         return r.value

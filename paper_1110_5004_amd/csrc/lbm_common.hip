@@ -183,22 +183,31 @@ hipError_t row_spread(const CaseDev& c, const float* phi, double level, double* 
   return hipGetLastError();
 }
 
-// F_a of Eq. 12 from discrete data: -u [(rho^n - rho^(n-1)) + div(rho u)^n],
-// rho = rho_G + phi drho, the divergence 3 sum_i w_i e_i . (rho u)(x + e_i)
-// over the lattice stencil with periodic wrap or mirror ghosts (the same
-// neighbour convention as every other stencil of the step).
-template <int LAT>
-__global__ void __launch_bounds__(256)
-k_fa_discrete(CaseDev c, const float* __restrict__ phi_prev, const float* __restrict__ phi,
-              FieldPtrs f, float* __restrict__ out) {
+// Neighbour coordinate g = x + d, |d| <= 1, on an axis of n nodes: the
+// periodic image, or the mirror ghost of a wall (ghost -1 -> node 0, ghost n
+// -> node n - 1), the neighbour convention of every stencil of the step.
+__device__ __forceinline__ int step_axis(int g, int n, int wall) {
+  if (g < 0) return wall ? 0 : n - 1;
+  if (g >= n) return wall ? n - 1 : 0;
+  return g;
+}
+
+// Launch shape of the node-parallel diagnostics: one grid row (y, z) per
+// blockIdx.x, x across blockIdx.y * blockDim.x + threadIdx.x, so that no
+// thread divides by a grid size.
+struct RowLaunch {
+  dim3 grid, block;
+};
+inline RowLaunch row_launch(const CaseDev& c) {
+  const int bx = c.nx >= 256 ? 256 : ((c.nx + 63) / 64) * 64;
+  return {dim3(c.ny * c.nz, (c.nx + bx - 1) / bx), dim3(bx)};
+}
+
+// Visits the Q - 1 moving directions of the lattice at node (x, y, z) as
+// fn(neighbour index, w_i, e_x, e_y, e_z).
+template <int LAT, class Fn>
+__device__ __forceinline__ void for_neighbours(const CaseDev& c, int x, int y, int z, Fn&& fn) {
   constexpr int Q = LAT == 0 ? d2q9::Q : d3q19::Q;
-  constexpr int DIM = LAT == 0 ? 2 : 3;
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= c.n) return;
-  const int x = idx % c.nx;
-  const int y = (idx / c.nx) % c.ny;
-  const int z = idx / (c.nx * c.ny);
-  float div = 0.0f;
 #pragma unroll
   for (int i = 1; i < Q; ++i) {
     int ex, ey, ez;
@@ -208,15 +217,33 @@ k_fa_discrete(CaseDev c, const float* __restrict__ phi_prev, const float* __rest
     } else {
       ex = d3q19::EX(i); ey = d3q19::EY(i); ez = d3q19::EZ(i); w = d3q19::WT(i);
     }
-    const int mx = map_axis(x + ex, c.nx, c.wall_x);
-    const int my = map_axis(y + ey, c.ny, c.wall_y);
-    const int mz = DIM == 3 ? map_axis(z + ez, c.nz, c.wall_z) : 0;
-    const unsigned j = mx + c.nx * (my + c.ny * mz);
+    const int mx = step_axis(x + ex, c.nx, c.wall_x);
+    const int my = step_axis(y + ey, c.ny, c.wall_y);
+    const int mz = LAT == 0 ? 0 : step_axis(z + ez, c.nz, c.wall_z);
+    fn((unsigned)(mx + c.nx * (my + c.ny * mz)), w, ex, ey, ez);
+  }
+}
+
+// F_a of Eq. 12 from discrete data: -u [(rho^n - rho^(n-1)) + div(rho u)^n],
+// rho = rho0 + drho phi, the divergence 3 sum_i w_i e_i . (rho u)(x + e_i).
+template <int LAT>
+__global__ void __launch_bounds__(256)
+k_fa_discrete(CaseDev c, const float* __restrict__ phi_prev, const float* __restrict__ phi,
+              FieldPtrs f, float* __restrict__ out) {
+  constexpr int DIM = LAT == 0 ? 2 : 3;
+  const int x = blockIdx.y * blockDim.x + threadIdx.x;
+  if (x >= c.nx) return;
+  const int row = blockIdx.x;
+  const int y = row % c.ny;
+  const int z = row / c.ny;
+  const unsigned idx = (unsigned)x + (unsigned)c.nx * row;
+  float div = 0.0f;
+  for_neighbours<LAT>(c, x, y, z, [&](unsigned j, float w, int ex, int ey, int ez) {
     const float rho = c.rho0 + phi[j] * c.drho;
     float eu = ex * f.u[0][j] + ey * f.u[1][j];
     if (DIM == 3) eu += ez * f.u[2][j];
     div += 3.0f * w * rho * eu;
-  }
+  });
   const float dt_rho = (phi[idx] - phi_prev[idx]) * c.drho;
 #pragma unroll
   for (int a = 0; a < DIM; ++a) out[(size_t)a * c.n + idx] = -f.u[a][idx] * (dt_rho + div);
@@ -224,13 +251,72 @@ k_fa_discrete(CaseDev c, const float* __restrict__ phi_prev, const float* __rest
 
 hipError_t fa_discrete(int lattice, const CaseDev& c, const float* phi_prev, const FieldPtrs& f,
                        float* out, hipStream_t stream) {
-  const int grid = (c.n + 255) / 256;
+  const RowLaunch L = row_launch(c);
+  if (L.grid.y > 65535u) return hipErrorInvalidConfiguration;
   if (lattice == 0)
-    hipLaunchKernelGGL(k_fa_discrete<0>, dim3(grid), dim3(256), 0, stream, c, phi_prev, f.phi,
-                       f, out);
+    hipLaunchKernelGGL(k_fa_discrete<0>, L.grid, L.block, 0, stream, c, phi_prev, f.phi, f, out);
   else
-    hipLaunchKernelGGL(k_fa_discrete<1>, dim3(grid), dim3(256), 0, stream, c, phi_prev, f.phi,
-                       f, out);
+    hipLaunchKernelGGL(k_fa_discrete<1>, L.grid, L.block, 0, stream, c, phi_prev, f.phi, f, out);
+  return hipGetLastError();
+}
+
+// F_a of Eq. 12 in Lee and Lin's form, Eq. 11: -u div[lambda grad(P - p)],
+// expanded as lambda lap q + grad lambda . grad q with q = P - p, the
+// isotropic central gradient 3 sum_i w_i e_i g(x + e_i) and Laplacian
+// 6 sum_i w_i (g(x + e_i) - g(x)).  P = phi theta' - theta is the equation of
+// state of the double well theta = beta (phi - phi_g)^2 (phi - phi_l)^2,
+// written as beta a b (2 phi (a + b) - a b) with a = phi - phi_g,
+// b = phi - phi_l; lambda = mu_dyn / (rho cs^2) = 3 (mu0 + dmu phi) /
+// (rho0 + drho phi).
+template <int LAT>
+__global__ void __launch_bounds__(256)
+k_fa_leelin(CaseDev c, WellArgs wa, FieldPtrs f, float* __restrict__ out) {
+  constexpr int DIM = LAT == 0 ? 2 : 3;
+  const int x = blockIdx.y * blockDim.x + threadIdx.x;
+  if (x >= c.nx) return;
+  const int row = blockIdx.x;
+  const int y = row % c.ny;
+  const int z = row / c.ny;
+  const unsigned idx = (unsigned)x + (unsigned)c.nx * row;
+  auto q_lam = [&](unsigned j, float& q, float& lam) {
+    const float ph = f.phi[j];
+    const float a = ph - wa.phi_g;
+    const float b = ph - wa.phi_l;
+    q = wa.beta * a * b * (2.0f * ph * (a + b) - a * b) - f.p[j];
+    lam = 3.0f * (c.mu0 + c.dmu * ph) / (c.rho0 + c.drho * ph);
+  };
+  float q0, l0;
+  q_lam(idx, q0, l0);
+  float gq[3] = {0.0f, 0.0f, 0.0f}, gl[3] = {0.0f, 0.0f, 0.0f};
+  float lap = 0.0f;
+  for_neighbours<LAT>(c, x, y, z, [&](unsigned j, float w, int ex, int ey, int ez) {
+    float q, l;
+    q_lam(j, q, l);
+    lap += w * (q - q0);
+    gq[0] += w * ex * q;
+    gq[1] += w * ey * q;
+    gl[0] += w * ex * l;
+    gl[1] += w * ey * l;
+    if (DIM == 3) {
+      gq[2] += w * ez * q;
+      gl[2] += w * ez * l;
+    }
+  });
+  float div = l0 * 6.0f * lap;
+#pragma unroll
+  for (int a = 0; a < DIM; ++a) div += 9.0f * gl[a] * gq[a];
+#pragma unroll
+  for (int a = 0; a < DIM; ++a) out[(size_t)a * c.n + idx] = -f.u[a][idx] * div;
+}
+
+hipError_t fa_leelin(int lattice, const CaseDev& c, const WellArgs& wa, const FieldPtrs& f,
+                     float* out, hipStream_t stream) {
+  const RowLaunch L = row_launch(c);
+  if (L.grid.y > 65535u) return hipErrorInvalidConfiguration;
+  if (lattice == 0)
+    hipLaunchKernelGGL(k_fa_leelin<0>, L.grid, L.block, 0, stream, c, wa, f, out);
+  else
+    hipLaunchKernelGGL(k_fa_leelin<1>, L.grid, L.block, 0, stream, c, wa, f, out);
   return hipGetLastError();
 }
 

@@ -67,6 +67,14 @@ hipError_t copy_bw(const float* in, float* out, long long n, hipStream_t stream)
 // fields f (phi, u) at n; out: dim planes of c.n floats.
 hipError_t fa_discrete(int lattice, const CaseDev& c, const float* phi_prev, const FieldPtrs& f,
                        float* out, hipStream_t stream);
+// F_a = -u div[lambda (grad P - grad p)] (Lee and Lin's form) from the dumped
+// fields f (phi, u, p); P = phi theta'(phi) - theta(phi) with theta =
+// beta (phi - phi_g)^2 (phi - phi_l)^2, lambda = 3 mu_dyn(phi) / rho(phi).
+struct WellArgs {
+  float beta, phi_g, phi_l;
+};
+hipError_t fa_leelin(int lattice, const CaseDev& c, const WellArgs& wa, const FieldPtrs& f,
+                     float* out, hipStream_t stream);
 // Per row in x of a node field phi: half the distance between the outermost
 // phi = level crossings, or -1 (out: c.ny * c.nz doubles).
 hipError_t row_spread(const CaseDev& c, const float* phi, double level, double* out,

@@ -652,6 +652,19 @@ int lbm_fa_discrete(lbm_handle* h, int32_t icase, const float* phi_prev, float* 
   return LBM_OK;
 }
 
+int lbm_fa_leelin(lbm_handle* h, int32_t icase, float* fa) {
+  if (!h || !fa || icase < 0 || icase >= h->ncases) return fail(LBM_ERR_ARG, "bad arguments");
+  lbm::FieldPtrs f = scratch_fields(h);
+  int rc = dump_fields(h, icase, f);
+  if (rc) return rc;
+  const lbm_case_params& p = h->prm[icase];
+  const bool sym = p.well == LBM_WELL_SYMMETRIC;
+  const lbm::WellArgs wa{(float)p.beta, (float)(sym ? -p.phi_star : 0.0),
+                         (float)(sym ? p.phi_star : 1.0)};
+  HIPCHK(lbm::fa_leelin(h->lattice == LBM_D2Q9 ? 0 : 1, h->cd[icase], wa, f, fa, h->stream));
+  return LBM_OK;
+}
+
 int lbm_spread_radius(lbm_handle* h, int32_t icase, double level, double* radius) {
   if (!h || !radius || icase < 0 || icase >= h->ncases) return fail(LBM_ERR_ARG, "bad arguments");
   if (!std::isfinite(level)) return fail(LBM_ERR_ARG, "level must be finite");

@@ -122,6 +122,9 @@ struct orc_sim {
   double *f, *g, *fn, *gn;        /* Q*N populations (current / scratch) */
   double *phi, *rho, *gphi, *lphi; /* N, N, dim*N, N */
   double *mu, *lmu, *u, *force, *pr, *gpsi, *tau;
+  /* remove_fa = 2: phi of the previous step (phi0 before the first), the
+   * velocity of the uncorrected recovery times rho, and the rate D */
+  double *phi_prev, *rhou, *grad, *dmass;
   double mass0;
   double gamma, drho, mu_l, mu_g;
   /* phi of the pure gas and liquid (0, 1 or -phi*, phi*) and the slope of
@@ -367,6 +370,7 @@ static int params_ok(const orc_params* p, const lat_t* L) {
   if (!(p->rho_l > 0.0) || !(p->rho_g > 0.0) || !(p->mu_ratio > 0.0)) return 0;
   if (p->well != 0 && p->well != 1) return 0;
   if (p->well == 1 && !(p->phi_star > 0.0)) return 0;
+  if (p->remove_fa < 0 || p->remove_fa > 2) return 0;
   return 1;
 }
 
@@ -398,6 +402,10 @@ orc_sim* orc_create(const orc_params* prm, const double* phi0, const double* u0,
   s->pr = alloc0(n);
   s->gpsi = alloc0(dim * n);
   s->tau = alloc0(n);
+  s->phi_prev = alloc0(n);
+  s->rhou = alloc0(dim * n);
+  s->grad = alloc0(dim * n);
+  s->dmass = alloc0(n);
 
   /* Theta_M = Gamma (tau_f - 1/2) for the BGK Cahn-Hilliard LBE. */
   s->gamma = prm->theta_m / (prm->tau_f - 0.5);
@@ -414,6 +422,7 @@ orc_sim* orc_create(const orc_params* prm, const double* phi0, const double* u0,
    * stencils as the step. */
   for (long idx = 0; idx < n; ++idx) {
     s->phi[idx] = phi0[idx];
+    s->phi_prev[idx] = phi0[idx];
     s->rho[idx] = rho_of(prm, phi0[idx]);
   }
   grad_lap_lat(&s->prm, &L, s->phi, s->gphi, s->lphi);
@@ -438,8 +447,9 @@ orc_sim* orc_create(const orc_params* prm, const double* phi0, const double* u0,
 
 void orc_destroy(orc_sim* s) {
   if (!s) return;
-  double* bufs[] = {s->f,  s->g,  s->fn,  s->gn,    s->phi, s->rho,  s->gphi, s->lphi,
-                    s->mu, s->lmu, s->u, s->force, s->pr,  s->gpsi, s->tau};
+  double* bufs[] = {s->f,   s->g,      s->fn,   s->gn,   s->phi,  s->rho,
+                    s->gphi, s->lphi, s->mu,   s->lmu,  s->u,    s->force,
+                    s->pr,  s->gpsi,  s->tau,  s->phi_prev, s->rhou, s->grad, s->dmass};
   for (size_t k = 0; k < sizeof bufs / sizeof bufs[0]; ++k) free(bufs[k]);
   free(s);
 }
@@ -473,8 +483,33 @@ static void sweep_fields(orc_sim* s, int want_lmu) {
     grad_lap_lat(p, L, s->mu, NULL, s->lmu);
   else
     memset(s->lmu, 0, (size_t)n * sizeof(double));
+  /* S1c': remove_fa = 2 takes the rate d_t rho + div(rho u) of Eq. 12 from
+   * the data instead of from Eq. 5: D = (rho^n - rho^(n-1)) +
+   * div(rho u_o), u_o the velocity the original model recovers at this step
+   * (D must not depend on the u it corrects, so that the recovery stays
+   * local and closed-form). */
+  if (p->remove_fa == 2) {
+#pragma omp parallel for schedule(static)
+    for (long idx = 0; idx < n; ++idx) {
+      double gb[QMAX], fsg[3] = {0, 0, 0}, grho[3] = {0, 0, 0}, uu[3], ff[3], pp;
+      for (int i = 0; i < q; ++i) gb[i] = s->g[i * n + idx];
+      for (int k = 0; k < dim; ++k) {
+        fsg[k] = s->mu[idx] * s->gphi[k * n + idx];
+        grho[k] = s->drho_dphi * s->gphi[k * n + idx];
+      }
+      fsg[vert] += -(s->rho[idx] - p->rho_ref) * p->gravity;
+      recover_lat(L, gb, s->rho[idx], fsg, 0.0, grho, uu, ff, &pp);
+      for (int k = 0; k < dim; ++k) s->rhou[k * n + idx] = s->rho[idx] * uu[k];
+    }
+    for (long idx = 0; idx < n; ++idx)
+      s->dmass[idx] = s->drho_dphi * (s->phi[idx] - s->phi_prev[idx]);
+    for (int a = 0; a < dim; ++a) {
+      grad_lap_lat(p, L, s->rhou + (long)a * n, s->grad, NULL);
+      for (long idx = 0; idx < n; ++idx) s->dmass[idx] += s->grad[(long)a * n + idx];
+    }
+  }
   /* S1d: forces, velocity, pressure. */
-  const double sw = p->remove_fa ? 1.0 : 0.0;
+  const double sw = p->remove_fa == 1 ? 1.0 : 0.0;
 #pragma omp parallel for schedule(static)
   for (long idx = 0; idx < n; ++idx) {
     double gb[QMAX], fsg[3] = {0, 0, 0}, grho[3] = {0, 0, 0}, uu[3], ff[3], pp;
@@ -485,6 +520,7 @@ static void sweep_fields(orc_sim* s, int want_lmu) {
     }
     fsg[vert] += -(s->rho[idx] - p->rho_ref) * p->gravity;   /* G */
     double c = sw * s->drho_dphi * p->theta_m * s->lmu[idx];  /* -F_a = c u */
+    if (p->remove_fa == 2) c = s->dmass[idx];
     recover_lat(L, gb, s->rho[idx], fsg, c, grho, uu, ff, &pp);
     for (int k = 0; k < dim; ++k) {
       s->u[k * n + idx] = uu[k];
@@ -558,6 +594,7 @@ static void stream(orc_sim* s) {
 void orc_step(orc_sim* s, long nsteps) {
   for (long k = 0; k < nsteps; ++k) {
     sweep_fields(s, 0);
+    memcpy(s->phi_prev, s->phi, (size_t)s->n * sizeof(double));
     collide(s);
     stream(s);
     s->time++;

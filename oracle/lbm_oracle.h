@@ -44,7 +44,10 @@ typedef struct {
   double mu_ratio;      /* dynamic viscosity ratio mu_L / mu_G */
   double gravity;       /* magnitude g of the body force G = -(rho - rho_ref) g e_vert */
   double rho_ref;       /* reference density of the body force */
-  int remove_fa;        /* 0: original model (F_a present), 1: corrected (adds -F_a) */
+  int remove_fa;        /* 0: original model (F_a present), 1: corrected (adds -F_a,
+                           F_a by Eq. 5), 2: corrected with F_a taken from the data,
+                           -u [(rho^n - rho^(n-1)) + div(rho u_o)], u_o the velocity of
+                           the uncorrected recovery at the same step */
   int well;             /* 0: theta = beta phi^2 (phi-1)^2, phi in [0, 1], rho by Eq. 4a;
                            1: symmetric theta = beta (phi^2 - phi*^2)^2 (Eq. 1b), phi in
                            [-phi*, phi*], rho by Eq. 4b */

@@ -294,7 +294,7 @@ def check_fixed_point(lib):
     of the step, to the last bit: mu = 0, K = 0, f = phi delta_i0, gbar = 0."""
     for lat, dims, wall in ((W.D2Q9, (8, 6, 1), (0, 1, 0)), (W.D3Q19, (4, 5, 6), (0, 0, 1))):
         for phi in (0.0, 1.0):
-            for rf in (0, 1):
+            for rf in (0, 1, 2):
                 case = _case(dims[0], dims[1], wall=wall, nz=dims[2], lattice=lat,
                              remove_fa=rf)
                 n = dims[0] * dims[1] * dims[2]
@@ -770,6 +770,48 @@ def check_fa_leelin(lib):
     assert np.allclose(np.sort(fx[0]), np.sort(f[0]), rtol=1e-12, atol=1e-20)
 
 
+def check_correction_from_data(lib):
+    """remove_fa = 2: the correction -F_a = D u with the rate D = (rho^n -
+    rho^(n-1)) + div(rho u_o) taken from the data.  At the populations of any
+    step, the velocity it recovers equals u_o rho / (rho - D / 2), where u_o is
+    the original model's velocity at the same populations (a remove_fa = 0
+    dump) and D is the rate of the pinned discrete estimator fa_discrete
+    (F = -u_o D) with phi^(n-1) the phi of the previous step -- at the first
+    step phi^(n-1) = phi^0, so only the divergence remains; phi and the
+    populations' mass are those of the original model."""
+    c = W.stationary_droplet(seed=2, n=40, radius=9.0, noise_amp=2e-3)
+    u0 = c.u0.copy()
+    u0[0] += 0.02
+    u0[1] -= 0.01
+    prm2 = dict(c.params, remove_fa=2, wall=[0, 1, 0])
+    prm0 = dict(prm2, remove_fa=0)
+    n = c.phi0.size
+
+    def check(sim, phi_prev):
+        got = sim.fields()
+        f, g = sim.get_state()
+        o = O.Sim(prm0, c.phi0, u0, c.p0, lib=lib)
+        o.set_state(f, g, sim.time)
+        ref = o.fields()
+        assert np.array_equal(got["phi"], ref["phi"])
+        uo = ref["u"]
+        fd = O.fa_discrete(prm0, phi_prev, ref["phi"], uo, lib=lib)
+        d = -(fd * uo).sum(axis=0) / (uo * uo).sum(axis=0)
+        rho = 0.1 + 0.9 * ref["phi"]
+        want = uo * rho / (rho - 0.5 * d)
+        assert np.allclose(got["u"], want, rtol=1e-11, atol=1e-18)
+        assert np.abs(got["u"] - uo).max() > 1e-9
+        return got
+
+    s = O.Sim(prm2, c.phi0, u0, c.p0, lib=lib)
+    first = check(s, s.fields()["phi"])
+    s.step(6)
+    prev = s.fields()["phi"]
+    s.step(1)
+    check(s, prev)
+    assert abs(s.diag()["mass"] - first["phi"].sum()) < 1e-12 * n
+
+
 def check_symmetric_well(lib):
     """The symmetric well of Eq. 1b, theta = beta (phi^2 - phi*^2)^2, with the
     density law of Eq. 4b, rho = rho_G + (phi + phi*) / (2 phi*) (rho_L - rho_G):
@@ -828,4 +870,4 @@ ALL_CHECKS = [check_lattice, check_feq_moments, check_geq_moments, check_source_
               check_shear_wave, check_ch_diffusion, check_switch_noop, check_fa_field,
               check_momentum_balance, check_correction_velocity, check_eq5_fa,
               check_advection, check_diagnostics, check_spread_radius, check_fa_discrete,
-              check_symmetric_well, check_fa_leelin]
+              check_symmetric_well, check_fa_leelin, check_correction_from_data]

@@ -84,6 +84,15 @@ MUTANTS = [
      "const double mud = mu_g + (phi_l - ph) / (phi_l - phi_g) * (mu_l - mu_g);"),
     ("theta_asym_power", "return p->beta * phi * phi * (phi - 1.0) * (phi - 1.0);",
      "return p->beta * phi * phi * (phi - 1.0);"),
+    ("data_rate_no_time_term",
+     "s->dmass[idx] = s->drho_dphi * (s->phi[idx] - s->phi_prev[idx]);",
+     "s->dmass[idx] = 0.0 * s->drho_dphi * (s->phi[idx] - s->phi_prev[idx]);"),
+    ("data_rate_phi_prev_frozen", "memcpy(s->phi_prev, s->phi, (size_t)s->n * sizeof(double));",
+     ";"),
+    ("data_rate_corrected_u", "for (int k = 0; k < dim; ++k) s->rhou[k * n + idx] = s->rho[idx] * uu[k];",
+     "for (int k = 0; k < dim; ++k) s->rhou[k * n + idx] = s->rho[idx] * s->u[k * n + idx];"),
+    ("data_rate_sign", "if (p->remove_fa == 2) c = s->dmass[idx];",
+     "if (p->remove_fa == 2) c = -s->dmass[idx];"),
 ]
 
 FAST_CHECKS = [c for c in P.ALL_CHECKS]

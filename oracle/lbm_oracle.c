@@ -456,6 +456,21 @@ void orc_destroy(orc_sim* s) {
 
 long orc_time(const orc_sim* s) { return s->time; }
 
+/* Force of Eq. 3 without the correction, F_s + G (F_s = mu grad phi, G along
+ * -vert), and grad rho, at node idx from the stencils of S1b. */
+static void node_forces(const orc_sim* s, long idx, double* fsg, double* grho) {
+  const orc_params* p = &s->prm;
+  const long n = s->n;
+  const int dim = s->L.dim;
+  const int vert = dim - 1; /* gravity acts along -y in 2-D and -z in 3-D */
+  for (int k = 0; k < 3; ++k) fsg[k] = grho[k] = 0.0;
+  for (int k = 0; k < dim; ++k) {
+    fsg[k] = s->mu[idx] * s->gphi[k * n + idx];   /* F_s = mu grad phi */
+    grho[k] = s->drho_dphi * s->gphi[k * n + idx];  /* grad rho */
+  }
+  fsg[vert] += -(s->rho[idx] - p->rho_ref) * p->gravity;   /* G */
+}
+
 /* S1a..S1e on the current populations.  want_lmu forces lap mu even for the
  * original model (used by the field dump for the F_a diagnostic). */
 static void sweep_fields(orc_sim* s, int want_lmu) {
@@ -463,7 +478,6 @@ static void sweep_fields(orc_sim* s, int want_lmu) {
   const lat_t* L = &s->L;
   const long n = s->n;
   const int q = L->q, dim = L->dim;
-  const int vert = dim - 1; /* gravity acts along -y in 2-D and -z in 3-D */
 
   /* S1a: order parameter and density. */
 #pragma omp parallel for schedule(static)
@@ -491,13 +505,9 @@ static void sweep_fields(orc_sim* s, int want_lmu) {
   if (p->remove_fa == 2) {
 #pragma omp parallel for schedule(static)
     for (long idx = 0; idx < n; ++idx) {
-      double gb[QMAX], fsg[3] = {0, 0, 0}, grho[3] = {0, 0, 0}, uu[3], ff[3], pp;
+      double gb[QMAX], fsg[3], grho[3], uu[3], ff[3], pp;
       for (int i = 0; i < q; ++i) gb[i] = s->g[i * n + idx];
-      for (int k = 0; k < dim; ++k) {
-        fsg[k] = s->mu[idx] * s->gphi[k * n + idx];
-        grho[k] = s->drho_dphi * s->gphi[k * n + idx];
-      }
-      fsg[vert] += -(s->rho[idx] - p->rho_ref) * p->gravity;
+      node_forces(s, idx, fsg, grho);
       recover_lat(L, gb, s->rho[idx], fsg, 0.0, grho, uu, ff, &pp);
       for (int k = 0; k < dim; ++k) s->rhou[k * n + idx] = s->rho[idx] * uu[k];
     }
@@ -512,13 +522,9 @@ static void sweep_fields(orc_sim* s, int want_lmu) {
   const double sw = p->remove_fa == 1 ? 1.0 : 0.0;
 #pragma omp parallel for schedule(static)
   for (long idx = 0; idx < n; ++idx) {
-    double gb[QMAX], fsg[3] = {0, 0, 0}, grho[3] = {0, 0, 0}, uu[3], ff[3], pp;
+    double gb[QMAX], fsg[3], grho[3], uu[3], ff[3], pp;
     for (int i = 0; i < q; ++i) gb[i] = s->g[i * n + idx];
-    for (int k = 0; k < dim; ++k) {
-      fsg[k] = s->mu[idx] * s->gphi[k * n + idx];   /* F_s = mu grad phi */
-      grho[k] = s->drho_dphi * s->gphi[k * n + idx];  /* grad rho */
-    }
-    fsg[vert] += -(s->rho[idx] - p->rho_ref) * p->gravity;   /* G */
+    node_forces(s, idx, fsg, grho);
     double c = sw * s->drho_dphi * p->theta_m * s->lmu[idx];  /* -F_a = c u */
     if (p->remove_fa == 2) c = s->dmass[idx];
     recover_lat(L, gb, s->rho[idx], fsg, c, grho, uu, ff, &pp);

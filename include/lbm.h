@@ -81,7 +81,18 @@ typedef struct {
   double rho_l, rho_g;       /* densities of Eq. 4a (> 0) */
   double mu_ratio;           /* mu_L / mu_G (> 0); = rho_l/rho_g gives constant nu */
   double gravity, rho_ref;   /* G = -(rho - rho_ref) gravity along -y (2-D) / -z (3-D) */
-  int32_t remove_fa;         /* 0: original model (F_a kept), 1: corrected (-F_a added) */
+  int32_t remove_fa;         /* 0: original model (F_a kept);
+                                1: corrected, -F_a = u drho theta_M lap mu added
+                                   (F_a evaluated through Eq. 5);
+                                2: corrected with the rate of Eq. 12 taken from
+                                   the data, -F_a = u [(rho^n - rho^(n-1)) +
+                                   div(rho u_o)], u_o the velocity the original
+                                   model recovers at the same step (so the
+                                   recovery stays closed-form), the time
+                                   difference over one step (zero at the first).
+                                   D2Q9 only; every case of the handle must use
+                                   it; each state copy then carries one more
+                                   float plane (phi of the step that wrote it). */
   int32_t storage;           /* LBM_FP32 / LBM_FP16 / LBM_BF16 (same for all cases) */
   double p0;                 /* rest pressure of the 16-bit g deviations */
   double scale_f, scale_g;   /* powers of two for 16-bit storage; 0 = automatic */

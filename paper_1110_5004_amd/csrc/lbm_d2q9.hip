@@ -75,14 +75,14 @@ __device__ __forceinline__ void grad_only(const float* s, int cx, int cy, float&
 // Velocity, total force and pressure from the moments of gbar:
 //   (rho - c/2) u = 3 sum e gbar + (F_s + G)/2,   F = F_s + G + c u,
 //   p = sum gbar + (1/6) drho u . grad phi        (u . grad p dropped),
-// with c = remove_fa drho theta_M lap mu, the cancelled -F_a = c u.
+// with cc the coefficient of the cancelled -F_a = c u: drho theta_M lap mu
+// (Eq. 5), the rate D taken from the data, or 0 (original model).
 __device__ __forceinline__ void recover(const CaseDev& c, float phi, float gx, float gy, float mu,
-                                        float lmu, float m0, float m1x, float m1y, float& ux,
+                                        float cc, float m0, float m1x, float m1y, float& ux,
                                         float& uy, float& p) {
   const float rho = c.rho0 + phi * c.drho;
   const float fsx = mu * gx;
   const float fsy = mu * gy - (rho - c.rho_ref) * c.gravity;
-  const float cc = c.corr * lmu;
   const float iden = __builtin_amdgcn_rcpf(rho - 0.5f * cc);
   ux = (3.0f * m1x + 0.5f * fsx) * iden;
   uy = (3.0f * m1y + 0.5f * fsy) * iden;
@@ -259,14 +259,17 @@ struct FieldOut {
   float* faz;
 };
 
-// LDS of one tile.
+// LDS of one tile.  RF = 0: original model; 1: lap mu formed (Eq. 5
+// correction, or the F_a dump); 2: correction from data.
 template <int TX, int TY, int RF>
 struct TileLds {
   static constexpr int R = RF ? 3 : 2;   // phi radius
   static constexpr int RM = R - 1;       // mu radius
+  static constexpr int MR = 1;           // radius of the gbar moments
   static constexpr int PW = TX + 2 * R, PH = TY + 2 * R;
   static constexpr int MW = TX + 2 * RM, MH = TY + 2 * RM;
   static constexpr int UW = TX + 2, UH = TY + 2;
+  static constexpr int VW = UW, VH = UH;  // moment region
   float ph[PW * PH];  // phi = ph + pl
   float pl[PW * PH];
   float mu[MW * MH];
@@ -276,6 +279,39 @@ struct TileLds {
   float gx[TX * TY];  // grad phi and lap mu of the tile nodes, kept from C for D
   float gy[TX * TY];
   float lm[TX * TY];
+  __device__ __forceinline__ float* m0() { return p; }
+  __device__ __forceinline__ float* m1x() { return ux; }
+  __device__ __forceinline__ float* m1y() { return uy; }
+};
+
+// RF = 2: the rate D = (rho^n - rho^(n-1)) + div(rho u_o) is needed at the
+// tile + 1, so u_o (the uncorrected velocity) at the tile + 2 and the gbar
+// moments there; phi^(n-1) at the tile + 1.
+template <int TX, int TY>
+struct TileLds<TX, TY, 2> {
+  static constexpr int R = 3, RM = 2, MR = 2;
+  static constexpr int PW = TX + 2 * R, PH = TY + 2 * R;
+  static constexpr int MW = TX + 2 * RM, MH = TY + 2 * RM;
+  static constexpr int UW = TX + 2, UH = TY + 2;
+  static constexpr int VW = TX + 2 * MR, VH = TY + 2 * MR;
+  float ph[PW * PH];
+  float pl[PW * PH];
+  float mu[MW * MH];
+  float g0[VW * VH];  // moments of gbar over the tile + 2
+  float g1x[VW * VH];
+  float g1y[VW * VH];
+  float qx[VW * VH];  // rho u_o over the tile + 2
+  float qy[VW * VH];
+  float pv[UW * UH];  // phi^(n-1) over the tile + 1
+  float ux[UW * UH];  // u, p over the tile + 1
+  float uy[UW * UH];
+  float p[UW * UH];
+  float gx[TX * TY];  // grad phi and D of the tile nodes, kept from C for D
+  float gy[TX * TY];
+  float lm[TX * TY];
+  __device__ __forceinline__ float* m0() { return g0; }
+  __device__ __forceinline__ float* m1x() { return g1x; }
+  __device__ __forceinline__ float* m1y() { return g1y; }
 };
 
 // Position k of the ring of width r around a TX x TY tile inside a region
@@ -316,10 +352,13 @@ struct TileLoads {
   using T = TileLds<TX, TY, RF>;
   static constexpr int NT = TX * TY / NPT;
   static constexpr int R = T::R;
+  static constexpr int MR = T::MR;
   static constexpr int NRA = T::PW * T::PH - TX * TY;  // phi ring
-  static constexpr int NRC = T::UW * T::UH - TX * TY;  // moment ring
+  static constexpr int NRC = T::VW * T::VH - TX * TY;  // moment ring
+  static constexpr int NPV = RF == 2 ? T::UW * T::UH : 0;  // phi^(n-1), tile + 1
   static constexpr int IA = (NRA + NT - 1) / NT;
   static constexpr int IC = (NRC + NT - 1) / NT;
+  static constexpr int IP = (NPV + NT - 1) / NT;
   float f0[NPT];
   uint16_t lo[NPT];
   Raw<S> fr[NPT][Q];
@@ -328,6 +367,7 @@ struct TileLoads {
   uint16_t alo[IA];
   Raw<S> afr[IA][Q];
   Raw<S> cgr[IC][Q];
+  float pvr[IP > 0 ? IP : 1];
   int tid = tile_tid();
 
   // Loads of one element: own node j, phi-ring slot it, moment-ring slot it.
@@ -361,13 +401,26 @@ struct TileLoads {
     const int k = tid + it * NT;
     if (k < NRC) {
       int lx, ly;
-      ring_pos<TX, TY, 1>(k, lx, ly);
-      int gx = x0 - 1 + lx, gy = y0 - 1 + ly;
+      ring_pos<TX, TY, MR>(k, lx, ly);
+      int gx = x0 - MR + lx, gy = y0 - MR + ly;
       if constexpr (!INNER) {
         gx = map_axis(gx, pu.c.nx, pu.c.wall_x);
         gy = map_axis(gy, pu.c.ny, pu.c.wall_y);
       }
       pu.gpop(gx, gy, cgr[it]);
+    }
+  }
+  // phi^(n-1) at position k of the tile + 1 (the mirror node beyond a wall)
+  template <bool INNER>
+  __device__ __forceinline__ void issue_pv(const Puller<S, INNER>& pu, int x0, int y0, int it) {
+    const int k = tid + it * NT;
+    if (k < NPV) {
+      int gx = x0 - 1 + k % T::UW, gy = y0 - 1 + k / T::UW;
+      if constexpr (!INNER) {
+        gx = map_axis(gx, pu.c.nx, pu.c.wall_x);
+        gy = map_axis(gy, pu.c.ny, pu.c.wall_y);
+      }
+      pvr[it] = gload<float>(pu.src, pu.c.phiv + 4u * (unsigned)(gx + pu.c.nx * gy));
     }
   }
 
@@ -385,10 +438,10 @@ struct TileLoads {
     L.pl[pk] = plo;
     float m0, m1x, m1y;
     g_sum<S>(c, gr[j], gv, m0, m1x, m1y);
-    const int uk = (ly0 + 1) * T::UW + (lx0 + 1);
-    L.p[uk] = m0;
-    L.ux[uk] = m1x;
-    L.uy[uk] = m1y;
+    const int uk = (ly0 + MR) * T::VW + (lx0 + MR);
+    L.m0()[uk] = m0;
+    L.m1x()[uk] = m1x;
+    L.m1y()[uk] = m1y;
     own.set(j, fv, gv, fr[j], gr[j]);
   }
   __device__ __forceinline__ void consume_phi(const CaseDev& c, T& L, int it) const {
@@ -406,12 +459,18 @@ struct TileLoads {
     const int k = tid + it * NT;
     if (k < NRC) {
       int lx, ly;
-      ring_pos<TX, TY, 1>(k, lx, ly);
+      ring_pos<TX, TY, MR>(k, lx, ly);
       float tmp[Q], m0, m1x, m1y;
       g_sum<S>(c, cgr[it], tmp, m0, m1x, m1y);
-      L.p[ly * T::UW + lx] = m0;
-      L.ux[ly * T::UW + lx] = m1x;
-      L.uy[ly * T::UW + lx] = m1y;
+      L.m0()[ly * T::VW + lx] = m0;
+      L.m1x()[ly * T::VW + lx] = m1x;
+      L.m1y()[ly * T::VW + lx] = m1y;
+    }
+  }
+  __device__ __forceinline__ void consume_pv(T& L, int it) const {
+    if constexpr (RF == 2) {
+      const int k = tid + it * NT;
+      if (k < NPV) L.pv[k] = pvr[it];
     }
   }
 
@@ -435,6 +494,11 @@ struct TileLoads {
     for (int it = 0; it < IC; ++it) {
       issue_mom<INNER>(pu, x0, y0, it);
       consume_mom(c, L, it);
+    }
+#pragma unroll
+    for (int it = 0; it < IP; ++it) {
+      issue_pv<INNER>(pu, x0, y0, it);
+      consume_pv(L, it);
     }
   }
 };
@@ -475,6 +539,72 @@ __device__ __forceinline__ void tile_bcd(TileLds<TX, TY, RF>& L, const CaseDev& 
   }
   __syncthreads();
 
+  if constexpr (RF == 2) {
+    // ---- C1: rho u_o over the tile + 2, u_o the velocity of the uncorrected
+    // recovery (the correction from data must not depend on the u it
+    // corrects).  Positions beyond a wall stand for their mirror node, as in C.
+    constexpr int VW = T::VW, VH = T::VH;
+    constexpr int IC1 = (VW * VH + NT - 1) / NT;
+#pragma unroll
+    for (int it = 0; it < IC1; ++it) {
+      const int k = tid + it * NT;
+      if (k < VW * VH) {
+        int lx = k % VW, ly = k / VW;
+        if constexpr (!INNER) {
+          lx = mirror_local(lx, x0 - 2, nx, c.wall_x, VW);
+          ly = mirror_local(ly, y0 - 2, ny, c.wall_y, VH);
+        }
+        const int pc = (ly + R - 2) * PW + (lx + R - 2);
+        float gx, gy;
+        grad_ff<PW>(phi, pc, gx, gy);
+        const float ph = L.ph[pc] + L.pl[pc];
+        const float mu = L.mu[ly * MW + lx];  // the mu region is the tile + 2
+        float ux, uy, p;
+        recover(c, ph, gx, gy, mu, 0.0f, L.g0[k], L.g1x[k], L.g1y[k], ux, uy, p);
+        const float rho = c.rho0 + ph * c.drho;
+        L.qx[k] = rho * ux;
+        L.qy[k] = rho * uy;
+      }
+    }
+    __syncthreads();
+    // ---- C2: over the tile + 1, the rate D = drho (phi - phi^(n-1)) +
+    // div(rho u_o), then u and p with -F_a = D u.
+#pragma unroll
+    for (int it = 0; it < ICC; ++it) {
+      const int k = tid + it * NT;
+      if (k < UW * UH) {
+        const int kx = k % UW, ky = k / UW;
+        int lx = kx, ly = ky;
+        if constexpr (!INNER) {
+          lx = mirror_local(lx, x0 - 1, nx, c.wall_x, UW);
+          ly = mirror_local(ly, y0 - 1, ny, c.wall_y, UH);
+        }
+        const int pc = (ly + R - 1) * PW + (lx + R - 1);
+        const int mx = lx + (RM - 1), my = ly + (RM - 1);
+        float gx, gy;
+        grad_ff<PW>(phi, pc, gx, gy);
+        const float ph = L.ph[pc] + L.pl[pc];
+        const float mu = L.mu[my * MW + mx];
+        float qxx, qxy, qyx, qyy;
+        grad_only<VW>(L.qx, lx + 1, ly + 1, qxx, qxy);
+        grad_only<VW>(L.qy, lx + 1, ly + 1, qyx, qyy);
+        const float dd = (ph - L.pv[k]) * c.drho + (qxx + qyy);
+        const int vk = (ky + 1) * VW + (kx + 1);  // the position's own moments
+        float ux, uy, p;
+        recover(c, ph, gx, gy, mu, dd, L.g0[vk], L.g1x[vk], L.g1y[vk], ux, uy, p);
+        L.ux[k] = ux;
+        L.uy[k] = uy;
+        L.p[k] = p;
+        const int tx = kx - 1, ty = ky - 1;
+        if (tx >= 0 && tx < TX && ty >= 0 && ty < TY) {
+          L.gx[ty * TX + tx] = gx;
+          L.gy[ty * TX + tx] = gy;
+          L.lm[ty * TX + tx] = dd;
+        }
+      }
+    }
+    __syncthreads();
+  } else {
   // ---- C: u, p over the tile + 1, in place of the moments.  A position
   // beyond a wall stands for its mirror node: its moments were pulled from
   // that node in A, and its stencils are read around the mirror position, so
@@ -497,8 +627,9 @@ __device__ __forceinline__ void tile_bcd(TileLds<TX, TY, RF>& L, const CaseDev& 
       const float ph = L.ph[pc] + L.pl[pc];
       const float mu = L.mu[my * MW + mx];
       const float lmu = RF ? lap_only<MW>(L.mu, mx, my) : 0.0f;
+      const float cc = c.corr * lmu;
       float ux, uy, p;
-      recover(c, ph, gx, gy, mu, lmu, L.p[k], L.ux[k], L.uy[k], ux, uy, p);
+      recover(c, ph, gx, gy, mu, cc, L.p[k], L.ux[k], L.uy[k], ux, uy, p);
       L.ux[k] = ux;
       L.uy[k] = uy;
       L.p[k] = p;
@@ -513,6 +644,7 @@ __device__ __forceinline__ void tile_bcd(TileLds<TX, TY, RF>& L, const CaseDev& 
     }
   }
   __syncthreads();
+  }
 
   // ---- D: collide (or dump fields) the own nodes
 #pragma unroll
@@ -529,7 +661,7 @@ __device__ __forceinline__ void tile_bcd(TileLds<TX, TY, RF>& L, const CaseDev& 
     const float ph = phh + phl;
     const float gx = L.gx[kk], gy = L.gy[kk];
     const float mu = L.mu[my * MW + mx];
-    const float lmu = L.lm[kk];
+    const float lmu = L.lm[kk];  // lap mu, or D for RF = 2
     const float ux = L.ux[uc];
     const float uy = L.uy[uc];
     const float p = L.p[uc];
@@ -540,11 +672,13 @@ __device__ __forceinline__ void tile_bcd(TileLds<TX, TY, RF>& L, const CaseDev& 
       fo.uy[idx] = uy;
       fo.p[idx] = p;
       fo.mu[idx] = mu;
-      fo.fax[idx] = -ux * c.fa_coef * lmu;
-      fo.fay[idx] = -uy * c.fa_coef * lmu;
+      // F_a by Eq. 5, whichever correction runs
+      const float lap_mu = RF == 2 ? lap_only<MW>(L.mu, mx, my) : lmu;
+      fo.fax[idx] = -ux * c.fa_coef * lap_mu;
+      fo.fay[idx] = -uy * c.fa_coef * lap_mu;
     } else {
       const float rho = c.rho0 + ph * c.drho;
-      const float cc = c.corr * lmu;
+      const float cc = RF == 2 ? lmu : c.corr * lmu;
       const float fx = mu * gx + cc * ux;
       const float fy = mu * gy - (rho - c.rho_ref) * c.gravity + cc * uy;
       float gpx, gpy;
@@ -595,6 +729,8 @@ __device__ __forceinline__ void tile_bcd(TileLds<TX, TY, RF>& L, const CaseDev& 
       float h0, e0;
       two_sum(phh, -fsum, h0, e0);
       op.put_f0(idx, h0, e0 + phl);
+      // the copy carries this step's phi, the next step's phi^(n-1)
+      if constexpr (RF == 2) gstore<float>(dst, c.phiv + 4u * idx, ph);
     }
   }
   __syncthreads();
@@ -633,6 +769,7 @@ __global__ void __launch_bounds__(TX * TY / NPT)
 __attribute__((amdgpu_waves_per_eu(WPE > 0 ? WPE : 1)))
 k_tile(const CaseDev* __restrict__ cases, const TileDev* __restrict__ tiles, int ntiles,
        int parity, FieldOut fo) {
+  static_assert(sizeof(TileLds<TX, TY, RF>) <= 160 * 1024, "tile exceeds the LDS of a CU");
   __shared__ TileLds<TX, TY, RF> lds;
   for (TileWalk w(ntiles); w.t < w.t_end; w.t += w.step) {
     const TileDev tl = tiles[w.t];
@@ -707,6 +844,8 @@ k_init(CaseDev c, int parity, const double* __restrict__ phi0, const double* __r
   float h0, e0;
   two_sum(nh[0], -fsum, h0, e0);
   P::put_f0(c, dst, idx, h0, e0 + nl[0]);
+  // correction from data: phi^(n-1) of the first step is phi0
+  if (c.phiv) gstore<float>(dst, c.phiv + 4u * idx, ph);
 }
 
 }  // namespace d2q9
@@ -726,13 +865,24 @@ hipError_t launch_step_t(const LaunchArgs& a) {
 template <int TX, int TY, int S>
 hipError_t launch_fields_t(const LaunchArgs& a, const FieldPtrs& f) {
   FieldOut fo{f.phi, f.u[0], f.u[1], f.u[2], f.p, f.mu, f.fa[0], f.fa[1], f.fa[2]};
-  hipLaunchKernelGGL((d2q9::k_tile<TX, TY, 1, 1, S, true, 0>), dim3(a.grid), dim3(TX * TY), 0,
-                     a.stream, a.cases, a.tiles, a.ntiles, a.parity, fo);
+  if (a.rf == 2)
+    hipLaunchKernelGGL((d2q9::k_tile<TX, TY, 1, 2, S, true, 0>), dim3(a.grid), dim3(TX * TY),
+                       0, a.stream, a.cases, a.tiles, a.ntiles, a.parity, fo);
+  else
+    hipLaunchKernelGGL((d2q9::k_tile<TX, TY, 1, 1, S, true, 0>), dim3(a.grid), dim3(TX * TY),
+                       0, a.stream, a.cases, a.tiles, a.ntiles, a.parity, fo);
   return hipGetLastError();
 }
 
 template <int TX, int TY, int NPT = 1, int WPE = 0>
 hipError_t launch_step_v(const LaunchArgs& a) {
+  if (a.rf == 2) {
+    switch (a.storage) {
+      case ST_FP32: return launch_step_t<TX, TY, NPT, 2, ST_FP32, WPE>(a);
+      case ST_FP16: return launch_step_t<TX, TY, NPT, 2, ST_FP16, WPE>(a);
+      default: return launch_step_t<TX, TY, NPT, 2, ST_BF16, WPE>(a);
+    }
+  }
   if (a.rf) {
     switch (a.storage) {
       case ST_FP32: return launch_step_t<TX, TY, NPT, 1, ST_FP32, WPE>(a);

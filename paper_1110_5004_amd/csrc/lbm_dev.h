@@ -38,11 +38,13 @@ struct CaseDev {
                     // 0, 1/2, 1 at a quarter, half, three quarters of the way
                     // from the gas to the liquid value of phi
   float gravity, rho_ref;
-  float corr;       // remove_fa * drho * theta_M  (coefficient of lap mu in -F_a / u)
+  float corr;       // drho * theta_M for remove_fa = 1, else 0 (coefficient of lap mu
+                    // in -F_a / u)
   float fa_coef;    // drho * theta_M           (F_a dump, whichever model runs)
   float p0;         // rest pressure of the 16-bit g deviations
   float scale_f, inv_scale_f, scale_g, inv_scale_g;
-  int pad1;
+  unsigned phiv;    // remove_fa = 2: byte offset, within a copy, of the float plane
+                    // holding phi of the step that wrote the copy; 0 otherwise
 };
 
 // theta'(phi) of the double well (Eq. 1a / 1b), with phi = hi + lo carried as
@@ -97,9 +99,13 @@ __device__ __forceinline__ float dec16(uint16_t h) {
 //               instead of the 6e-8 of one float
 //   FP16/BF16:  one float plane (f_0), then 2q-1 16-bit planes
 //               (f_1..f_{q-1}, g_0..g_{q-1})
-__host__ __device__ inline size_t copy_bytes(int storage, int q, long long stride) {
-  return storage == ST_FP32 ? (size_t)(2 * q) * 4 * stride + (size_t)2 * stride
-                            : (size_t)4 * stride + (size_t)(2 * q - 1) * 2 * stride;
+// then, with phi_plane, one float plane of phi (the correction from data needs
+// phi one step back; a copy carries the phi of the step that wrote it).
+__host__ __device__ inline size_t copy_bytes(int storage, int q, long long stride,
+                                             bool phi_plane = false) {
+  const size_t pops = storage == ST_FP32 ? (size_t)(2 * q) * 4 * stride + (size_t)2 * stride
+                                         : (size_t)4 * stride + (size_t)(2 * q - 1) * 2 * stride;
+  return pops + (phi_plane ? (size_t)4 * stride : 0);
 }
 
 // Error-free transformation s + e = a + b (round to nearest, no reassociation).

@@ -64,6 +64,11 @@ int validate(const lbm_case_params* cs, int32_t n) {
       return fail(LBM_ERR_ARG, "case %d: unknown lattice %d", k, c.lattice);
     if (c.lattice != cs[0].lattice)
       return fail(LBM_ERR_ARG, "case %d: all cases of a handle must share the lattice", k);
+    if ((c.remove_fa == 2) != (cs[0].remove_fa == 2))
+      return fail(LBM_ERR_ARG,
+                  "case %d: remove_fa = 2 cannot be mixed with 0 / 1 in one handle", k);
+    if (c.remove_fa == 2 && c.lattice != LBM_D2Q9)
+      return fail(LBM_ERR_ARG, "case %d: remove_fa = 2 is implemented for D2Q9", k);
     if (c.storage != cs[0].storage)
       return fail(LBM_ERR_ARG, "case %d: all cases of a handle must share the storage", k);
     if (c.storage < LBM_FP32 || c.storage > LBM_BF16)
@@ -75,7 +80,8 @@ int validate(const lbm_case_params* cs, int32_t n) {
       return fail(LBM_ERR_ARG, "case %d: nz must be >= 4 for D3Q19", k);
     if (nodes_of(c) > (1LL << 30)) return fail(LBM_ERR_ARG, "case %d: too many nodes", k);
     // kernels address one copy of the populations with 32-bit byte offsets
-    if (lbm::copy_bytes(c.storage, q_of(c.lattice), stride_of(c)) >= (1ULL << 32))
+    if (lbm::copy_bytes(c.storage, q_of(c.lattice), stride_of(c), c.remove_fa == 2) >=
+        (1ULL << 32))
       return fail(LBM_ERR_ARG, "case %d: one copy of the populations exceeds 4 GiB", k);
     for (int a = 0; a < 3; ++a)
       if (c.bc[a] != LBM_PERIODIC && c.bc[a] != LBM_WALL)
@@ -90,8 +96,8 @@ int validate(const lbm_case_params* cs, int32_t n) {
       return fail(LBM_ERR_ARG, "case %d: densities and viscosity ratio must be > 0", k);
     if (c.theta_m < 0.0 || c.beta < 0.0 || c.kappa < 0.0)
       return fail(LBM_ERR_ARG, "case %d: theta_m, beta, kappa must be >= 0", k);
-    if (c.remove_fa != 0 && c.remove_fa != 1)
-      return fail(LBM_ERR_ARG, "case %d: remove_fa must be 0 or 1", k);
+    if (c.remove_fa < 0 || c.remove_fa > 2)
+      return fail(LBM_ERR_ARG, "case %d: remove_fa must be 0, 1 or 2", k);
     if (c.well != LBM_WELL_ASYMMETRIC && c.well != LBM_WELL_SYMMETRIC)
       return fail(LBM_ERR_ARG, "case %d: well must be LBM_WELL_ASYMMETRIC or LBM_WELL_SYMMETRIC", k);
     if (c.well == LBM_WELL_SYMMETRIC && !(c.phi_star > 0.0 && std::isfinite(c.phi_star)))
@@ -180,7 +186,8 @@ Layout plan(const lbm_case_params* cs, int n) {
   L.state_off.resize(2 * n);
   long long nmax = 0;
   for (int k = 0; k < n; ++k) {
-    const size_t cb = align_up(lbm::copy_bytes(cs[k].storage, q, stride_of(cs[k])));
+    const size_t cb =
+        align_up(lbm::copy_bytes(cs[k].storage, q, stride_of(cs[k]), cs[k].remove_fa == 2));
     L.state_off[2 * k] = at;
     at += cb;
     L.state_off[2 * k + 1] = at;
@@ -276,7 +283,10 @@ CaseDev derive(const lbm_case_params& p, char* s0, char* s1) {
   c.wb = (float)(-2.0 * phi_g / (phi_l - phi_g) - 0.5);
   c.gravity = (float)p.gravity;
   c.rho_ref = (float)p.rho_ref;
-  c.corr = (float)(p.remove_fa ? drho * p.theta_m : 0.0);
+  c.corr = (float)(p.remove_fa == 1 ? drho * p.theta_m : 0.0);
+  c.phiv = p.remove_fa == 2
+               ? (unsigned)lbm::copy_bytes(p.storage, q_of(p.lattice), stride_of(p), false)
+               : 0u;
   c.fa_coef = (float)(drho * p.theta_m);
   c.p0 = (float)p.p0;
   // 16-bit scales: FP16 keeps deviations down to ~1e-8 normal with 2^13;
@@ -383,7 +393,7 @@ int dump_fields(lbm_handle* h, int icase, const lbm::FieldPtrs& f) {
   a.grid = round8(a.ntiles);
   a.parity = h->parity;
   a.storage = h->storage;
-  a.rf = 1;
+  a.rf = h->rf == 2 ? 2 : 1;
   a.stream = h->stream;
   HIPCHK(lbm::d2q9_fields(a, f));
   return LBM_OK;
@@ -483,7 +493,9 @@ int lbm_init(const lbm_case_params* cases, int32_t ncases, const double* const* 
   h->L = L;
   h->stream = reinterpret_cast<hipStream_t>(hip_stream);
   h->check_every = check_every;
-  for (int k = 0; k < ncases; ++k) h->rf |= cases[k].remove_fa;
+  // kernel form: 2 (correction from data, every case), 1 (lap mu formed;
+  // a case with remove_fa = 0 has corr = 0), or 0
+  for (int k = 0; k < ncases; ++k) h->rf = std::max(h->rf, (int)cases[k].remove_fa);
   if (dev_arena) {
     h->arena = reinterpret_cast<char*>(dev_arena);
   } else {
@@ -699,7 +711,7 @@ int lbm_info(const lbm_handle* h, int32_t* ncases, int64_t* step, int32_t* stora
 
 int lbm_state_bytes(const lbm_handle* h, int32_t icase, size_t* bytes) {
   if (!h || !bytes || icase < 0 || icase >= h->ncases) return fail(LBM_ERR_ARG, "bad arguments");
-  *bytes = lbm::copy_bytes(h->storage, h->q, h->cd[icase].stride);
+  *bytes = lbm::copy_bytes(h->storage, h->q, h->cd[icase].stride, h->rf == 2);
   return LBM_OK;
 }
 

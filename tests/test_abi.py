@@ -48,9 +48,10 @@ def _params(**kw):
 
 
 @pytest.mark.parametrize("bad", [dict(tau_f=0.5), dict(tau_g=0.3), dict(rho_g=0.0),
-                                 dict(nx=3), dict(nz=2), dict(remove_fa=2),
+                                 dict(nx=3), dict(nz=2),
                                  dict(wall=[0, 2, 0]), dict(mu_ratio=-1.0),
-                                 dict(theta_m=float("nan")), dict(well=2),
+                                 dict(theta_m=float("nan")), dict(well=2), dict(remove_fa=3),
+                                 dict(remove_fa=2, lattice=1, nz=8),
                                  dict(well=1, phi_star=0.0, beta=0.01, kappa=0.01),
                                  dict(well=1, phi_star=float("inf"), beta=0.01, kappa=0.01)])
 def test_invalid_parameters_rejected(L, bad):
@@ -76,3 +77,21 @@ def test_required_bytes_grows_with_storage(L):
 def test_variants_listed(L):
     v = B.variants(B.D2Q9)
     assert len(v) >= 2 and all(t[2] == 1 for t in v)
+
+
+def test_correction_modes_not_mixed(L):
+    """remove_fa = 2 keeps an extra phi plane in the state, so a handle holds
+    either only remove_fa = 2 cases or none."""
+    arr = (B.CaseParams * 2)(B.make_case(_params(remove_fa=2)), B.make_case(_params(remove_fa=1)))
+    nbytes = C.c_size_t()
+    assert L.lbm_required_bytes(arr, 2, C.byref(nbytes)) == B.ERR_ARG
+    arr = (B.CaseParams * 2)(B.make_case(_params(remove_fa=2)), B.make_case(_params(remove_fa=2)))
+    assert L.lbm_required_bytes(arr, 2, C.byref(nbytes)) == 0
+    one = C.c_size_t()
+    c1 = B.make_case(_params(remove_fa=1))
+    assert L.lbm_required_bytes(C.byref(c1), 1, C.byref(one)) == 0
+    two = C.c_size_t()
+    c2 = B.make_case(_params(remove_fa=2))
+    assert L.lbm_required_bytes(C.byref(c2), 1, C.byref(two)) == 0
+    # two copies, each with one more float plane (16 x 16 nodes, padded to 256)
+    assert two.value - one.value == 2 * 4 * 256

@@ -4,18 +4,21 @@
  * The library advances the incompressible two-distribution phase-field LB
  * model analysed by Li, Luo & Gao, "Additional interfacial force in lattice
  * Boltzmann models for incompressible multiphase flows" (arXiv:1110.5004):
- *   - order parameter phi with bulk free energy beta phi^2 (phi-1)^2 and
- *     gradient coefficient kappa (Eq. 1a), chemical potential
- *     mu = theta'(phi) - kappa lap phi, convective Cahn-Hilliard transport with
- *     mobility theta_M (Eq. 2) solved by a BGK order-parameter distribution f;
- *   - density rho = rho_G + phi (rho_L - rho_G) (Eq. 4a);
+ *   - order parameter phi with bulk free energy beta phi^2 (phi-1)^2 (Eq. 1a)
+ *     or beta (phi^2 - phi*^2)^2 (Eq. 1b) and gradient coefficient kappa,
+ *     chemical potential mu = theta'(phi) - kappa lap phi, convective
+ *     Cahn-Hilliard transport with mobility theta_M (Eq. 2) solved by a BGK
+ *     order-parameter distribution f;
+ *   - density linear in phi (Eq. 4a, or Eq. 4b with the symmetric well);
  *   - pressure distribution g with the forcing K of Eq. 8, surface force
  *     F_s = mu grad phi and body force G = -(rho - rho_ref) g e_vertical;
  *   - a switch that keeps the additional force F_a = -u [d_t rho + div(rho u)]
- *     of Eq. 12 (original model) or cancels it by adding -F_a, evaluated as
- *     u (rho_L - rho_G) theta_M lap mu via Eq. 5, to the forcing (corrected
- *     model, paragraph after Eq. 12);
- *   - isotropic central stencils for grad and lap (splash-test paragraph).
+ *     of Eq. 12 (original model) or cancels it by adding -F_a to the forcing
+ *     (corrected model, paragraph after Eq. 12), with d_t rho + div(rho u)
+ *     evaluated through Eq. 5 or taken from the data;
+ *   - isotropic central stencils for grad and lap (splash-test paragraph);
+ *   - diagnostics: FP64 reductions, the spread radius of the paper's Fig. 5,
+ *     F_a from discrete data and in Lee and Lin's form (Eq. 11).
  * D2Q9 follows the paper; D3Q19 is the same model on 19 velocities.
  *
  * Conventions for every function:

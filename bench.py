@@ -11,7 +11,8 @@ of the fused step kernel (algorithmic bytes 148 B per lattice update in FP32:
 18 float populations plus the 2-byte low part of f_0, read once and written
 once), the FP64 CPU oracle timed on a
 bounded sample of the same workload, and the same measurements for FP16
-storage (76 B per update) and the original model.
+storage (76 B per update), the original model and the correction with F_a's
+rate taken from the data (156 B per update in FP32).
 """
 import argparse
 import json
@@ -24,6 +25,9 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_LU = {"fp32": 148.0, "fp16": 76.0, "bf16": 76.0}
+# the correction from data (remove_fa = 2) also reads and writes one float of
+# phi per node
+PHI_PLANE_BYTES = 8.0
 BYTES_PER_LU_3D = {"fp32": 308.0, "fp16": 156.0, "bf16": 156.0}
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "traffic.json")
 
@@ -34,7 +38,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=20000)
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--storage", default="fp32")
-    ap.add_argument("--remove-fa", type=int, default=1)
+    ap.add_argument("--remove-fa", type=int, default=1, choices=[0, 1, 2])
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-extra", action="store_true", help="skip the FP16 / original-model legs")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -340,7 +344,7 @@ def main():
 
     main_leg = leg(torch, W, hip, a.storage, a.remove_fa, a.steps, a.warmup, a.workload,
                    a.variant)
-    bpl = BYTES_PER_LU[a.storage]
+    bpl = BYTES_PER_LU[a.storage] + (PHI_PLANE_BYTES if a.remove_fa == 2 else 0.0)
     achieved = main_leg["nodes"] * bpl / (main_leg["seconds"] / a.steps) / 1e9
     key = f"{a.workload}_{a.storage}_rf{a.remove_fa}_v{main_leg['variant']}"
     step_s = main_leg["seconds"] / a.steps
@@ -379,9 +383,13 @@ def main():
     }
     if not a.no_extra:
         extra = {}
-        for st, rf in (("fp16", a.remove_fa), ("bf16", a.remove_fa), (a.storage, 1 - a.remove_fa)):
+        other = [0, 1, 2]
+        other.remove(a.remove_fa)
+        for st, rf in [("fp16", a.remove_fa), ("bf16", a.remove_fa)] + \
+                [(a.storage, r) for r in other]:
             r = leg(torch, W, hip, st, rf, a.steps, a.warmup, a.workload)
-            ach = r["nodes"] * BYTES_PER_LU[st] / (r["seconds"] / a.steps) / 1e9
+            bpl_rf = BYTES_PER_LU[st] + (PHI_PLANE_BYTES if rf == 2 else 0.0)
+            ach = r["nodes"] * bpl_rf / (r["seconds"] / a.steps) / 1e9
             extra[f"{st}_rf{rf}"] = dict(mlups=round(r["mlups"], 1),
                                          achieved_gbs=round(ach, 1),
                                          frac=round(ach / HBM_PEAK_GBS, 4),

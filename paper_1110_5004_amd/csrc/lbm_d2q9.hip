@@ -115,23 +115,39 @@ struct InnerPtrs {
   }
 };
 
-// Byte offset of f_i (or g_i) pulled by node (x, y) = idx: the neighbour
-// x - e_i, or (across a wall) the node itself in the opposite direction.
-// INNER: the neighbour is known to lie inside the grid.
-template <int S, bool INNER, bool G>
-__device__ __forceinline__ unsigned pull_ofs(const CaseDev& c, int x, int y, unsigned idx,
-                                             int i) {
+// A load coordinate g of a tile or its halo mapped into the grid: the
+// periodic image or the wall mirror, then clamped.  Every position a real
+// node reads lies at most R + 1 <= 4 <= n outside the grid, where one fold is
+// exact; positions farther out occur only in the unused part of a ragged
+// tile, where the clamp keeps the load in bounds.
+__device__ __forceinline__ int fold_axis(int g, int n, int wall) {
+  if (g < 0) g = wall ? -g - 1 : g + n;
+  else if (g >= n) g = wall ? 2 * n - 1 - g : g - n;
+  return min(max(g, 0), n - 1);
+}
+
+// Near the boundary: byte offset of f_i (G = false) or g_i pulled by the
+// in-grid node idx, whose position is flagged at the grid's edges (x0: x = 0,
+// x1: x = nx - 1, y0, y1 likewise).  The source is the neighbour x - e_i,
+// wrapped across a periodic seam, or (across a wall) the node itself in the
+// opposite direction.  e_i is a compile-time constant, so each axis takes one
+// flag and the offset is formed without branches.
+template <int S, bool G>
+__device__ __forceinline__ unsigned edge_ofs(const CaseDev& c, unsigned idx, bool x0, bool x1,
+                                             bool y0, bool y1, int i) {
   using P = Pops<S, Q>;
   if (i == 0) return G ? P::gofs(c, 0, idx) : P::fofs(c, 0, idx);
-  if constexpr (INNER) {
-    const unsigned j = idx - EX(i) - c.nx * EY(i);
-    return G ? P::gofs(c, i, j) : P::fofs(c, i, j);
-  } else {
-    bool bb;
-    const unsigned j = pull_src(c, x, y, 0, EX(i), EY(i), 0, &bb);
-    if constexpr (G) return bb ? P::gofs(c, OPP(i), idx) : P::gofs(c, i, j);
-    else return bb ? P::fofs(c, OPP(i), idx) : P::fofs(c, i, j);
-  }
+  const int ex = EX(i), ey = EY(i);
+  const bool hx = ex > 0 ? x0 : (ex < 0 ? x1 : false);  // x - e_x leaves the grid
+  const bool hy = ey > 0 ? y0 : (ey < 0 ? y1 : false);
+  const bool bb = (hx && c.wall_x) || (hy && c.wall_y);
+  const int nxy = c.nx * c.ny;
+  int j = (int)idx - ex - c.nx * ey;
+  j += (hx && !c.wall_x) ? (ex > 0 ? c.nx : -c.nx) : 0;
+  j += (hy && !c.wall_y) ? (ey > 0 ? nxy : -nxy) : 0;
+  const unsigned own = G ? P::gofs(c, OPP(i), idx) : P::fofs(c, OPP(i), idx);
+  const unsigned pulled = G ? P::gofs(c, i, (unsigned)j) : P::fofs(c, i, (unsigned)j);
+  return bb ? own : pulled;
 }
 
 // Raw loads of the populations a node pulls.  FV: f_0, its low part and
@@ -142,26 +158,32 @@ struct Puller {
   const char* src;
   InnerPtrs<S> ip;
   __device__ __forceinline__ Puller(const CaseDev& cc, const char* s) : c(cc), src(s), ip(cc, s) {}
+  // node index of an in-grid position (sides < 2^24, checked at set-up)
+  __device__ __forceinline__ unsigned node(int x, int y) const {
+    return (unsigned)x + __umul24((unsigned)c.nx, (unsigned)y);
+  }
   __device__ __forceinline__ void fpop(int x, int y, float& f0, uint16_t& lo, Raw<S>* fr) const {
     using P = Pops<S, Q>;
-    const unsigned idx = x + c.nx * y;
+    const unsigned idx = node(x, y);
     constexpr unsigned W = sizeof(Raw<S>);
+    const bool x0 = x == 0, x1 = x == c.nx - 1, y0 = y == 0, y1 = y == c.ny - 1;
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
       if constexpr (INNER) fr[i] = gload<Raw<S>>(ip.f[i], W * idx);
-      else fr[i] = gload<Raw<S>>(src, pull_ofs<S, false, false>(c, x, y, idx, i));
+      else fr[i] = gload<Raw<S>>(src, edge_ofs<S, false>(c, idx, x0, x1, y0, y1, i));
     }
     f0 = INNER ? gload<float>(ip.f[0], 4u * idx) : gload<float>(src, P::fofs(c, 0, idx));
     if constexpr (S == ST_FP32) lo = gload<uint16_t>(ip.f0lo, 2u * idx);
     else lo = 0;
   }
   __device__ __forceinline__ void gpop(int x, int y, Raw<S>* gr) const {
-    const unsigned idx = x + c.nx * y;
+    const unsigned idx = node(x, y);
     constexpr unsigned W = sizeof(Raw<S>);
+    const bool x0 = x == 0, x1 = x == c.nx - 1, y0 = y == 0, y1 = y == c.ny - 1;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
       if constexpr (INNER) gr[i] = gload<Raw<S>>(ip.g[i], W * idx);
-      else gr[i] = gload<Raw<S>>(src, pull_ofs<S, false, true>(c, x, y, idx, i));
+      else gr[i] = gload<Raw<S>>(src, edge_ofs<S, true>(c, idx, x0, x1, y0, y1, i));
     }
   }
 };
@@ -376,8 +398,8 @@ struct TileLoads {
     const int kk = tid + j * NT;
     int mx = x0 + kk % TX, my = y0 + kk / TX;
     if constexpr (!INNER) {
-      mx = map_axis(mx, pu.c.nx, pu.c.wall_x);
-      my = map_axis(my, pu.c.ny, pu.c.wall_y);
+      mx = fold_axis(mx, pu.c.nx, pu.c.wall_x);
+      my = fold_axis(my, pu.c.ny, pu.c.wall_y);
     }
     pu.fpop(mx, my, f0[j], lo[j], fr[j]);
     pu.gpop(mx, my, gr[j]);
@@ -390,8 +412,8 @@ struct TileLoads {
       ring_pos<TX, TY, R>(k, lx, ly);
       int gx = x0 - R + lx, gy = y0 - R + ly;
       if constexpr (!INNER) {
-        gx = map_axis(gx, pu.c.nx, pu.c.wall_x);
-        gy = map_axis(gy, pu.c.ny, pu.c.wall_y);
+        gx = fold_axis(gx, pu.c.nx, pu.c.wall_x);
+        gy = fold_axis(gy, pu.c.ny, pu.c.wall_y);
       }
       pu.fpop(gx, gy, af0[it], alo[it], afr[it]);
     }
@@ -404,8 +426,8 @@ struct TileLoads {
       ring_pos<TX, TY, MR>(k, lx, ly);
       int gx = x0 - MR + lx, gy = y0 - MR + ly;
       if constexpr (!INNER) {
-        gx = map_axis(gx, pu.c.nx, pu.c.wall_x);
-        gy = map_axis(gy, pu.c.ny, pu.c.wall_y);
+        gx = fold_axis(gx, pu.c.nx, pu.c.wall_x);
+        gy = fold_axis(gy, pu.c.ny, pu.c.wall_y);
       }
       pu.gpop(gx, gy, cgr[it]);
     }
@@ -417,10 +439,10 @@ struct TileLoads {
     if (k < NPV) {
       int gx = x0 - 1 + k % T::UW, gy = y0 - 1 + k / T::UW;
       if constexpr (!INNER) {
-        gx = map_axis(gx, pu.c.nx, pu.c.wall_x);
-        gy = map_axis(gy, pu.c.ny, pu.c.wall_y);
+        gx = fold_axis(gx, pu.c.nx, pu.c.wall_x);
+        gy = fold_axis(gy, pu.c.ny, pu.c.wall_y);
       }
-      pvr[it] = gload<float>(pu.src, pu.c.phiv + 4u * (unsigned)(gx + pu.c.nx * gy));
+      pvr[it] = gload<float>(pu.src, pu.c.phiv + 4u * pu.node(gx, gy));
     }
   }
 

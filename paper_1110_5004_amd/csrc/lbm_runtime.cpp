@@ -74,6 +74,9 @@ int validate(const lbm_case_params* cs, int32_t n) {
     if (c.storage < LBM_FP32 || c.storage > LBM_BF16)
       return fail(LBM_ERR_ARG, "case %d: unknown storage %d", k, c.storage);
     if (c.nx < 4 || c.ny < 4) return fail(LBM_ERR_ARG, "case %d: nx, ny must be >= 4", k);
+    // node indices are formed with 24-bit multiplies
+    if (c.nx >= (1 << 24) || c.ny >= (1 << 24) || c.nz >= (1 << 24))
+      return fail(LBM_ERR_ARG, "case %d: every side must be < 2^24", k);
     if (c.lattice == LBM_D2Q9 && c.nz != 1)
       return fail(LBM_ERR_ARG, "case %d: nz must be 1 for D2Q9", k);
     if (c.lattice == LBM_D3Q19 && c.nz < 4)

@@ -22,7 +22,7 @@ def _key(sim):
     p = sim.params[0]
     nodes = sum(int(d[0] * d[1] * d[2]) for d in sim.dims)
     bucket = 2 ** int(round(math.log2(max(nodes, 1))))
-    rf = int(any(q["remove_fa"] for q in sim.params))
+    rf = max(int(q["remove_fa"]) for q in sim.params)
     st = sim.storage_name
     return f"lat{p['lattice']}_{st}_rf{rf}_n{bucket}_c{len(sim.dims)}"
 

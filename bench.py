@@ -329,7 +329,7 @@ def main_3d(a, torch, W, hip):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "one GPU only: the step has no multi-GPU path, --gpus must be 1"}))
         sys.exit(2)
     import torch
     import paper_1110_5004_amd as hip

@@ -95,3 +95,16 @@ def test_correction_modes_not_mixed(L):
     assert L.lbm_required_bytes(C.byref(c2), 1, C.byref(two)) == 0
     # two copies, each with one more float plane (16 x 16 nodes, padded to 256)
     assert two.value - one.value == 2 * 4 * 256
+
+
+def test_copy_over_4gib_rejected(L):
+    """Kernels address a state copy with 32-bit byte offsets: 8192 x 7000 D2Q9
+    nodes at 74 B fit, 8192 x 7100 do not (nor 8192 x 7000 with the extra
+    phi plane of the correction from data, 78 B)."""
+    nbytes = C.c_size_t()
+    ok = B.make_case(_params(nx=8192, ny=7000))
+    assert L.lbm_required_bytes(C.byref(ok), 1, C.byref(nbytes)) == 0
+    for kw in (dict(ny=7100), dict(ny=7000, remove_fa=2)):
+        c = B.make_case(_params(nx=8192, **kw))
+        assert L.lbm_required_bytes(C.byref(c), 1, C.byref(nbytes)) == B.ERR_ARG
+        assert "4 GiB" in L.lbm_last_error().decode()

@@ -1,0 +1,115 @@
+"""Edge cases of the grid size on the GPU path, through the C ABI.
+
+Largest: a D2Q9 grid whose state copy is just under the 4 GiB that 32-bit
+byte offsets address (8192 x 7000 nodes at 74 B each; 8192 x 6700 at 78 B
+with the phi plane of the correction from data).  A droplet near the far
+end of the node range must evolve to the same bits as the same droplet in a
+small grid: a step reads a node's neighbourhood within 4 nodes, so after k
+steps nothing beyond 4k nodes of the droplet has changed, and every node is
+computed by the same arithmetic from the same inputs.
+
+Smallest: 4 x 4 (and 5 x 4, 4 x 4 x 4) grids, where every tile shape is larger
+than the grid and most of each tile lies outside it, against the oracle."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def hip():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1110_5004_amd as P
+    P.lib()
+    return P
+
+
+def droplet_case(nx, ny, centre, rf):
+    """Periodic grid, droplet of radius 20 moving down at 0.03."""
+    prm = W.base_params(W.D2Q9, nx, ny, 1, (0, 0, 0), sigma=0.01, remove_fa=rf)
+    phi, u, p = W.droplet_fields(prm, centre, 20.0, impact_u=0.03)
+    return W.Case(prm, phi, u, p)
+
+
+def _largest(hip, rf):
+    import torch
+    # 74 B per node, 78 B with the phi plane of the correction from data
+    big_n = (8192, 7000 if rf == 1 else 6700)
+    steps = 12
+    # the same fractional centre, so that both grids see bit-identical inputs
+    cb = (4000.3, 6450.6)
+    small = 256
+    cs = (128.3, 128.6)
+    sim = hip.Simulation([droplet_case(*big_n, cb, rf)])
+    per_copy = sim.state_bytes()
+    print(f"largest rf={rf}: {big_n[0]} x {big_n[1]}, {per_copy} B per state copy")
+    assert 0.98 * 2**32 < per_copy < 2**32
+    sim.step(steps)
+    d = sim.diagnostics()
+    m = sim.moments_device()
+    x0, y0 = int(cb[0]) - 128, int(cb[1]) - 128
+    assert y0 + small <= big_n[1] and x0 + small <= big_n[0]
+    win = (slice(y0, y0 + small), slice(x0, x0 + small))
+    phi_b = m["phi"].view(big_n[1], big_n[0])[win].cpu().numpy()
+    u_b = m["u"].view(2, big_n[1], big_n[0])[(slice(None),) + win].cpu().numpy()
+    p_b = m["p"].view(big_n[1], big_n[0])[win].cpu().numpy()
+    del m
+    sim.close()
+    torch.cuda.empty_cache()
+    ref = hip.Simulation([droplet_case(small, small, cs, rf)])
+    ref.step(steps)
+    r = ref.moments()
+    ref.close()
+    assert d["nonfinite"] == 0 and d["mass_drift_rel"] <= 1e-6
+    assert np.array_equal(phi_b, r["phi"].reshape(small, small))
+    assert np.array_equal(u_b, r["u"].reshape(2, small, small))
+    assert np.array_equal(p_b, r["p"].reshape(small, small))
+
+
+@pytest.mark.parametrize("rf", [1, 2])
+def test_largest_copy_matches_small_grid(hip, rf):
+    """A state copy just under 4 GiB (8192 x 7000 nodes; 8192 x 6700 with the
+    phi plane), droplet at (4000.3, 6450.6), 12 steps: the window around it
+    equals a 256 x 256 grid's run bit for bit."""
+    _largest(hip, rf)
+
+
+@pytest.mark.parametrize("dims,wall", [((4, 4, 1), (0, 0, 0)), ((4, 4, 1), (1, 1, 0)),
+                                       ((5, 4, 1), (0, 1, 0)), ((4, 4, 4), (0, 0, 1))])
+@pytest.mark.parametrize("rf", [0, 1])
+def test_smallest_grids(hip, dims, wall, rf):
+    nx, ny, nz = dims
+    lat = W.D2Q9 if nz == 1 else W.D3Q19
+    n = nx * ny * nz
+    prm = W.base_params(lat, nx, ny, nz, wall, sigma=0.01, remove_fa=rf, width=2.0)
+    x = np.tile(np.arange(nx, dtype=float), ny * nz)
+    y = np.repeat(np.tile(np.arange(ny, dtype=float), nz), nx)
+    phi = 0.5 + 0.3 * np.sin(2 * np.pi * x / nx) * np.cos(2 * np.pi * y / ny)
+    rng = np.random.default_rng(n + rf)
+    dim = 2 if nz == 1 else 3
+    u = rng.normal(0, 2e-3, (dim, n))
+    case = W.Case(prm, phi, u, np.zeros(n))
+    steps = 50
+    ref = O.Sim(case.params, case.phi0, case.u0, case.p0)
+    ref.step(steps)
+    want = ref.fields()
+    first = None
+    for v in range(len(hip.variants(lat))):
+        sim = hip.Simulation([case])
+        sim.set_launch(v, 0, 16)
+        sim.step(steps)
+        if first is None:
+            got = sim.moments()
+            dphi = float(np.abs(got["phi"].astype(np.float64) - want["phi"]).max())
+            du = float(np.linalg.norm(got["u"].astype(np.float64) - want["u"]) /
+                       np.linalg.norm(want["u"]))
+            print(f"smallest {dims} {wall} rf={rf}: max|dphi|={dphi:.2e} relL2(u)={du:.2e}")
+            assert dphi <= 1e-5 and du <= 1e-4
+            first = sim.get_state()
+        else:
+            assert np.array_equal(sim.get_state(), first), f"variant {v} differs"
+        sim.close()

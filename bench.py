@@ -252,23 +252,46 @@ def pull_copy_ceiling(torch, hip, lattice, storage, dims, reps=200):
     return t
 
 
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(W, seconds):
     """The FP64 oracle as it stands on the host cores, on the same workload,
-    stepping until about `seconds` have passed."""
+    stepping until about `seconds` have passed with all the OpenMP threads it
+    gets, then a third as long on one thread."""
+    import ctypes
     from oracle import oracle as O
+    gomp = ctypes.CDLL("libgomp.so.1")
     case = W.splash_2d(remove_fa=1)
     s = O.Sim(case.params, case.phi0, case.u0, case.p0)
     s.step(1)
-    t0 = time.perf_counter()
-    steps = 0
-    while time.perf_counter() - t0 < seconds:
-        s.step(2)
-        steps += 2
-    dt = time.perf_counter() - t0
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return dict(value=case.n * steps / dt / 1e6, unit="MLUPS", cores=cores, kind="oracle",
+
+    def rate(limit):
+        t0 = time.perf_counter()
+        steps = 0
+        while time.perf_counter() - t0 < limit:
+            s.step(2)
+            steps += 2
+        dt = time.perf_counter() - t0
+        return case.n * steps / dt / 1e6, steps, dt
+
+    threads = gomp.omp_get_max_threads()
+    value, steps, dt = rate(seconds)
+    gomp.omp_set_num_threads(1)
+    one, steps1, dt1 = rate(seconds / 3)
+    gomp.omp_set_num_threads(threads)
+    return dict(value=value, unit="MLUPS", cores=threads, kind="oracle",
                 sample=f"{steps} steps of the 1024x512 splash workload (corrected model), "
-                       f"{dt:.1f} s, FP64")
+                       f"{dt:.1f} s, FP64; then {steps1} steps on one thread, {dt1:.1f} s",
+                value_one_thread=one, cpu_model=_cpu_model())
 
 
 STEP_KERNEL_SOURCES = ("lbm_d2q9.hip", "lbm_dev.h", "lbm_lattice.h")

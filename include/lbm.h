@@ -93,9 +93,9 @@ typedef struct {
                                    model recovers at the same step (so the
                                    recovery stays closed-form), the time
                                    difference over one step (zero at the first).
-                                   D2Q9 only; every case of the handle must use
-                                   it; each state copy then carries one more
-                                   float plane (phi of the step that wrote it). */
+                                   Every case of the handle must use it; each
+                                   state copy then carries one more float plane
+                                   (phi of the step that wrote it). */
   int32_t storage;           /* LBM_FP32 / LBM_FP16 / LBM_BF16 (same for all cases) */
   double p0;                 /* rest pressure of the 16-bit g deviations */
   double scale_f, scale_g;   /* powers of two for 16-bit storage; 0 = automatic */

@@ -55,6 +55,7 @@ struct Fields3 {
   float *phh, *phl, *m0, *m1x, *m1y, *m1z;  // pull
   float* mu;                                // mu
   float *ux, *uy, *uz, *p, *lmu, *gx, *gy, *gz;  // fields
+  float* dd;  // correction from data: the rate D of -F_a = D u
 };
 
 // ---- 1: pull, phi, moments
@@ -116,15 +117,17 @@ __device__ __forceinline__ void grad_f(const CaseDev& c, const float* f, int x, 
 // position, so that it equals the mirror node's mu as the step defines it.
 // Stencil sums run over i = 1..18 in lattice order, as in the node-parallel
 // definition, so the result does not depend on the tile shape.
-template <int TX, int TY, int TZ>
+template <int TX, int TY, int TZ, bool RF2>
 struct FieldTile {
   static constexpr int NT = TX * TY * TZ;
   static constexpr int PX = TX + 4, PY = TY + 4, PZ = TZ + 4;  // phi region
   static constexpr int MX = TX + 2, MY = TY + 2, MZ = TZ + 2;  // mu region
   static constexpr int NP = PX * PY * PZ, NM = MX * MY * MZ;
+  static constexpr int NQ = RF2 ? NM : 1;
   float ph[NP];
   float pl[NP];
   float mu[NM];
+  float qx[NQ], qy[NQ], qz[NQ];  // RF2: rho u_o over the mu region
 };
 
 // Offset of neighbour e_i in a region of row pitch X and plane pitch X * Y.
@@ -133,10 +136,14 @@ __device__ __forceinline__ constexpr int nofs(int i) {
   return EX(i) + X * (EY(i) + Y * EZ(i));
 }
 
-template <int TX, int TY, int TZ>
+// RF2 (correction from data): also rho u_o over the tile + 1, u_o the
+// uncorrected recovery from the moment planes, then at each node the rate
+// D = drho (phi - phi^(n-1)) + div(rho u_o), with phi^(n-1) from the plane of
+// the current state copy, in place of the Eq. 5 coefficient.
+template <int TX, int TY, int TZ, bool RF2>
 __global__ void __launch_bounds__(TX * TY * TZ)
-k3_fields_t(CaseDev c, Fields3 fl, int want_lmu) {
-  using T = FieldTile<TX, TY, TZ>;
+k3_fields_t(CaseDev c, Fields3 fl, int want_lmu, int parity) {
+  using T = FieldTile<TX, TY, TZ, RF2>;
   constexpr int PX = T::PX, PY = T::PY, MX = T::MX, MY = T::MY;
   __shared__ T L;
   // XCD-aware tile order: workgroup b runs on XCD b % 8 and takes the b / 8-th
@@ -209,6 +216,46 @@ k3_fields_t(CaseDev c, Fields3 fl, int want_lmu) {
   }
   __syncthreads();
 
+  if constexpr (RF2) {
+    // rho u_o over the tile + 1; a position beyond a wall stands for its
+    // mirror node (its stencils around the mirror position, as for mu, and
+    // the mirror node's moments)
+    for (int k = tid; k < T::NM; k += T::NT) {
+      const int ax = k % MX, ay = (k / MX) % MY, az = k / (MX * MY);
+      int mx = ax, my = ay, mz = az;
+      int qx = x0 - 1 + ax, qy = y0 - 1 + ay, qz = z0 - 1 + az;
+      if (!inner) {
+        mx = mirror_local(mx, x0 - 1, c.nx, c.wall_x, MX);
+        my = mirror_local(my, y0 - 1, c.ny, c.wall_y, MY);
+        mz = mirror_local(mz, z0 - 1, c.nz, c.wall_z, T::MZ);
+        qx = map_axis(qx, c.nx, c.wall_x);
+        qy = map_axis(qy, c.ny, c.wall_y);
+        qz = map_axis(qz, c.nz, c.wall_z);
+      }
+      const unsigned q = qx + c.nx * (qy + c.ny * qz);
+      const int pc = (mx + 1) + PX * ((my + 1) + PY * (mz + 1));
+      const float h0 = L.ph[pc], l0 = L.pl[pc];
+      float g[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+      for (int i = 1; i < Q; ++i) {
+        const int j = pc + nofs<PX, PY>(i);
+        const float d = (L.ph[j] - h0) + (L.pl[j] - l0);
+        const float w = i <= 6 ? (1.0f / 6.0f) : (1.0f / 12.0f);
+        if (EX(i)) g[0] += EX(i) > 0 ? w * d : -w * d;
+        if (EY(i)) g[1] += EY(i) > 0 ? w * d : -w * d;
+        if (EZ(i)) g[2] += EZ(i) > 0 ? w * d : -w * d;
+      }
+      const float rho = c.rho0 + (h0 + l0) * c.drho;
+      const float mu = L.mu[k];
+      const float iden = __builtin_amdgcn_rcpf(rho);
+      const float fsz = mu * g[2] - (rho - c.rho_ref) * c.gravity;
+      L.qx[k] = rho * ((3.0f * fl.m1x[q] + 0.5f * (mu * g[0])) * iden);
+      L.qy[k] = rho * ((3.0f * fl.m1y[q] + 0.5f * (mu * g[1])) * iden);
+      L.qz[k] = rho * ((3.0f * fl.m1z[q] + 0.5f * fsz) * iden);
+    }
+    __syncthreads();
+  }
+
   // the tile's own nodes
   if (!own) return;
   const int pc = (lx + 2) + PX * ((ly + 2) + PY * (lz + 2));
@@ -241,7 +288,23 @@ k3_fields_t(CaseDev c, Fields3 fl, int want_lmu) {
   // (rho - c/2) u = 3 sum e gbar + (F_s + G)/2, gravity along -z
   const float fsx = mu * g[0], fsy = mu * g[1];
   const float fsz = mu * g[2] - (rho - c.rho_ref) * c.gravity;
-  const float cc = c.corr * lmu;
+  float cc = c.corr * lmu;
+  if constexpr (RF2) {
+    const char* src = parity ? c.state[1] : c.state[0];
+    float dv = 0.0f;
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+      const int j = mc + nofs<MX, MY>(i);
+      const float w = i <= 6 ? (1.0f / 6.0f) : (1.0f / 12.0f);  // 3 w_i
+      float e = 0.0f;
+      if (EX(i)) e += EX(i) > 0 ? L.qx[j] : -L.qx[j];
+      if (EY(i)) e += EY(i) > 0 ? L.qy[j] : -L.qy[j];
+      if (EZ(i)) e += EZ(i) > 0 ? L.qz[j] : -L.qz[j];
+      dv += w * e;
+    }
+    cc = (ph - gload<float>(src, c.phiv + 4u * idx)) * c.drho + dv;
+    fl.dd[idx] = cc;
+  }
   const float iden = __builtin_amdgcn_rcpf(rho - 0.5f * cc);
   const float ux = (3.0f * m1x + 0.5f * fsx) * iden;
   const float uy = (3.0f * m1y + 0.5f * fsy) * iden;
@@ -260,7 +323,7 @@ k3_fields_t(CaseDev c, Fields3 fl, int want_lmu) {
 // ---- 4: collision and store
 // Per-node inputs of the collision (all at the node itself, ∇p included).
 struct NodeFields {
-  float phh, phl, mu, lmu, p, ux, uy, uz, gx, gy, gz, gpx, gpy, gpz;
+  float phh, phl, mu, cc, p, ux, uy, uz, gx, gy, gz, gpx, gpy, gpz;  // cc: -F_a = cc u
 };
 
 // grad psi, the regrouped BGK collision of f and gbar with the Eq. 8 forcing
@@ -274,7 +337,7 @@ __device__ __forceinline__ void collide_node(const CaseDev& c, const OutPtrs<S, 
   const float ph = n.phh + n.phl;
   const float ux = n.ux, uy = n.uy, uz = n.uz, p = n.p, mu = n.mu;
   const float rho = c.rho0 + ph * c.drho;
-  const float cc = c.corr * n.lmu;
+  const float cc = n.cc;
   const float fx = mu * n.gx + cc * ux;
   const float fy = mu * n.gy + cc * uy;
   const float fz = mu * n.gz - (rho - c.rho_ref) * c.gravity + cc * uz;
@@ -350,7 +413,7 @@ __global__ void __launch_bounds__(256) k3_collide(CaseDev c, int parity, Fields3
   n.phh = fl.phh[idx];
   n.phl = fl.phl[idx];
   n.mu = fl.mu[idx];
-  n.lmu = fl.lmu[idx];
+  n.cc = c.phiv ? fl.dd[idx] : c.corr * fl.lmu[idx];
   n.p = fl.p[idx];
   n.ux = fl.ux[idx];
   n.uy = fl.uy[idx];
@@ -362,6 +425,8 @@ __global__ void __launch_bounds__(256) k3_collide(CaseDev c, int parity, Fields3
   n.gpy = gp[1];
   n.gpz = gp[2];
   collide_node<S>(c, op, idx, fv, gv, n);
+  // correction from data: the copy carries this step's phi
+  if (c.phiv) gstore<float>(dst, c.phiv + 4u * idx, n.phh + n.phl);
 }
 
 // ---- field dump for lbm_moments / diagnostics
@@ -431,6 +496,8 @@ k3_init(CaseDev c, int parity, const double* __restrict__ phi0, const double* __
   float hh, ee;
   two_sum(h0, -fsum, hh, ee);
   P::put_f0(c, dst, idx, hh, ee + l0);
+  // correction from data: phi^(n-1) of the first step is phi0
+  if (c.phiv) gstore<float>(dst, c.phiv + 4u * idx, ph);
 }
 
 }  // namespace d3q19
@@ -460,14 +527,20 @@ d3q19::Fields3 fields3(const Field3Ptrs& f) {
   fl.gx = f.plane[12];
   fl.gy = f.plane[13];
   fl.gz = f.plane[14];
+  fl.dd = f.plane[15];
   return fl;
 }
 
 template <int FX, int FY, int FZ>
-void launch_fields_t(const CaseDev& c, const d3q19::Fields3& fl, int want_lmu, hipStream_t s) {
+void launch_fields_t(const CaseDev& c, const d3q19::Fields3& fl, int want_lmu, int parity,
+                     hipStream_t s) {
   const int ft = ((c.nx + FX - 1) / FX) * ((c.ny + FY - 1) / FY) * ((c.nz + FZ - 1) / FZ);
-  hipLaunchKernelGGL((d3q19::k3_fields_t<FX, FY, FZ>), dim3(8 * ((ft + 7) / 8)),
-                     dim3(FX * FY * FZ), 0, s, c, fl, want_lmu);
+  if (c.phiv)
+    hipLaunchKernelGGL((d3q19::k3_fields_t<FX, FY, FZ, true>), dim3(8 * ((ft + 7) / 8)),
+                       dim3(FX * FY * FZ), 0, s, c, fl, want_lmu, parity);
+  else
+    hipLaunchKernelGGL((d3q19::k3_fields_t<FX, FY, FZ, false>), dim3(8 * ((ft + 7) / 8)),
+                       dim3(FX * FY * FZ), 0, s, c, fl, want_lmu, parity);
 }
 
 template <int S>
@@ -476,11 +549,11 @@ hipError_t pipeline(int variant, const CaseDev& c, int parity, const d3q19::Fiel
   const int grid = (c.n + 255) / 256;
   hipLaunchKernelGGL(d3q19::k3_pull<S>, dim3(grid), dim3(256), 0, s, c, parity, fl);
   switch (variant) {
-    case 0: launch_fields_t<16, 8, 4>(c, fl, want_lmu, s); break;
-    case 1: launch_fields_t<32, 4, 4>(c, fl, want_lmu, s); break;
-    case 2: launch_fields_t<32, 8, 2>(c, fl, want_lmu, s); break;
-    case 3: launch_fields_t<16, 16, 2>(c, fl, want_lmu, s); break;
-    case 4: launch_fields_t<8, 8, 8>(c, fl, want_lmu, s); break;
+    case 0: launch_fields_t<16, 8, 4>(c, fl, want_lmu, parity, s); break;
+    case 1: launch_fields_t<32, 4, 4>(c, fl, want_lmu, parity, s); break;
+    case 2: launch_fields_t<32, 8, 2>(c, fl, want_lmu, parity, s); break;
+    case 3: launch_fields_t<16, 16, 2>(c, fl, want_lmu, parity, s); break;
+    case 4: launch_fields_t<8, 8, 8>(c, fl, want_lmu, parity, s); break;
     default: return hipErrorInvalidValue;
   }
   if (collide) hipLaunchKernelGGL(d3q19::k3_collide<S>, dim3(grid), dim3(256), 0, s, c, parity, fl);

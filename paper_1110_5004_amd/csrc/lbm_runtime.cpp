@@ -67,8 +67,6 @@ int validate(const lbm_case_params* cs, int32_t n) {
     if ((c.remove_fa == 2) != (cs[0].remove_fa == 2))
       return fail(LBM_ERR_ARG,
                   "case %d: remove_fa = 2 cannot be mixed with 0 / 1 in one handle", k);
-    if (c.remove_fa == 2 && c.lattice != LBM_D2Q9)
-      return fail(LBM_ERR_ARG, "case %d: remove_fa = 2 is implemented for D2Q9", k);
     if (c.storage != cs[0].storage)
       return fail(LBM_ERR_ARG, "case %d: all cases of a handle must share the storage", k);
     if (c.storage < LBM_FP32 || c.storage > LBM_BF16)

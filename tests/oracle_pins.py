@@ -778,32 +778,41 @@ def check_correction_from_data(lib):
     dump) and D is the rate of the pinned discrete estimator fa_discrete
     (F = -u_o D) with phi^(n-1) the phi of the previous step -- at the first
     step phi^(n-1) = phi^0, so only the divergence remains; phi and the
-    populations' mass are those of the original model."""
+    populations' mass are those of the original model.  D2Q9 and D3Q19."""
     c = W.stationary_droplet(seed=2, n=40, radius=9.0, noise_amp=2e-3)
     u0 = c.u0.copy()
     u0[0] += 0.02
     u0[1] -= 0.01
-    prm2 = dict(c.params, remove_fa=2, wall=[0, 1, 0])
+    _check_data_rate(lib, dict(c.params, remove_fa=2, wall=[0, 1, 0]), c.phi0, u0, c.p0)
+    prm = W.base_params(W.D3Q19, 14, 12, 10, (0, 0, 1), sigma=0.01, remove_fa=2)
+    rng = np.random.default_rng(3)
+    phi, u, p = W.droplet_fields(prm, (6.3, 5.8, 5.1), 3.5, impact_u=0.02,
+                                 noise=rng.normal(0, 2e-3, (3, 14 * 12 * 10)))
+    u[0] += 0.01
+    _check_data_rate(lib, prm, phi, u, p)
+
+
+def _check_data_rate(lib, prm2, phi0, u0, p0):
     prm0 = dict(prm2, remove_fa=0)
-    n = c.phi0.size
+    n = phi0.size
 
     def check(sim, phi_prev):
         got = sim.fields()
         f, g = sim.get_state()
-        o = O.Sim(prm0, c.phi0, u0, c.p0, lib=lib)
+        o = O.Sim(prm0, phi0, u0, p0, lib=lib)
         o.set_state(f, g, sim.time)
         ref = o.fields()
         assert np.array_equal(got["phi"], ref["phi"])
         uo = ref["u"]
         fd = O.fa_discrete(prm0, phi_prev, ref["phi"], uo, lib=lib)
         d = -(fd * uo).sum(axis=0) / (uo * uo).sum(axis=0)
-        rho = 0.1 + 0.9 * ref["phi"]
+        rho = prm2["rho_g"] + (prm2["rho_l"] - prm2["rho_g"]) * ref["phi"]
         want = uo * rho / (rho - 0.5 * d)
         assert np.allclose(got["u"], want, rtol=1e-11, atol=1e-18)
         assert np.abs(got["u"] - uo).max() > 1e-9
         return got
 
-    s = O.Sim(prm2, c.phi0, u0, c.p0, lib=lib)
+    s = O.Sim(prm2, phi0, u0, p0, lib=lib)
     first = check(s, s.fields()["phi"])
     s.step(6)
     prev = s.fields()["phi"]

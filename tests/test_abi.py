@@ -51,7 +51,6 @@ def _params(**kw):
                                  dict(nx=3), dict(nz=2),
                                  dict(wall=[0, 2, 0]), dict(mu_ratio=-1.0),
                                  dict(theta_m=float("nan")), dict(well=2), dict(remove_fa=3),
-                                 dict(remove_fa=2, lattice=1, nz=8),
                                  dict(well=1, phi_star=0.0, beta=0.01, kappa=0.01),
                                  dict(well=1, phi_star=float("inf"), beta=0.01, kappa=0.01)])
 def test_invalid_parameters_rejected(L, bad):

@@ -192,3 +192,56 @@ def test_three_models_on_the_falling_droplet(hip):
     print("falling droplet t=1.9e4 (centroid y, spread radius): original "
           f"{res[0][0]:.3f} {res[0][1]:.3f}; Eq. 5 correction {res[1][0]:.3f} {res[1][1]:.3f}; "
           f"correction from data {res[2][0]:.3f} {res[2][1]:.3f}")
+
+
+def droplet3d(dims, wall, seed):
+    nx, ny, nz = dims
+    prm = W.base_params(W.D3Q19, nx, ny, nz, wall, sigma=0.01, gravity=2e-5, remove_fa=2,
+                        tau_g=0.7, mu_ratio=4.0)
+    rng = np.random.default_rng(seed)
+    phi, u, p = W.droplet_fields(prm, (nx * 0.45, ny * 0.5, nz * 0.55), min(dims) * 0.3,
+                                 impact_u=0.02, noise=rng.normal(0, 1e-3, (3, nx * ny * nz)))
+    return W.Case(prm, phi, u, p)
+
+
+@pytest.mark.parametrize("dims,wall", [((20, 18, 16), (0, 0, 1)), ((17, 21, 19), (1, 1, 1))])
+def test_d3q19_parity_every_variant(hip, dims, wall):
+    """D3Q19, moving droplet with gravity and walls, 120 steps, at the FP32
+    bounds; every fields-tile shape gives the same bits."""
+    case = droplet3d(dims, wall, seed=sum(dims))
+    sim = hip.Simulation([case])
+    sim.step(120)
+    dphi, du = errors(sim.moments(), oracle_run(case, 120).fields())
+    print(f"correction from data d3q19 {dims} {wall}: max|dphi|={dphi:.2e} relL2(u)={du:.2e}")
+    assert dphi <= PHI_TOL and du <= U_TOL
+    first = sim.get_state()
+    sim.close()
+    for variant in range(1, len(hip.variants(hip.D3Q19))):
+        other = hip.Simulation([case])
+        other.set_launch(variant, 0, 16)
+        other.step(120)
+        assert np.array_equal(other.get_state(), first), f"variant {variant} differs"
+        other.close()
+
+
+def test_d3q19_first_steps_and_dump(hip):
+    """D3Q19: dumps at steps 0, 1, 2 and 7 (phi^(n-1) = phi0 at the first),
+    and a checkpoint that carries the phi plane."""
+    case = droplet3d((16, 14, 12), (0, 1, 1), seed=2)
+    sim = hip.Simulation([case])
+    ref = O.Sim(case.params, case.phi0, case.u0, case.p0)
+    for steps in (0, 1, 1, 5):
+        if steps:
+            sim.step(steps)
+            ref.step(steps)
+        got, want = sim.moments(), ref.fields()
+        dphi, du = errors(got, want)
+        assert dphi <= 1e-6 and du <= 1e-5, (sim.time, dphi, du)
+        assert np.abs(got["mu"] - want["mu"]).max() <= 1e-4 * np.abs(want["mu"]).max()
+        assert np.abs(got["fa"] - want["fa"]).max() <= 2e-3 * np.abs(want["fa"]).max()
+    st = sim.get_state()
+    sim.step(20)
+    other = hip.Simulation([case])
+    other.set_state(st, step=7)
+    other.step(20)
+    assert np.array_equal(other.get_state(), sim.get_state())

@@ -33,22 +33,85 @@ __device__ __forceinline__ unsigned nbr(const CaseDev& c, int x, int y, int z, i
   return mx + c.nx * (my + c.ny * mz);
 }
 
-__device__ __forceinline__ bool is_interior(const CaseDev& c, int x, int y, int z) {
-  return x > 0 && x < c.nx - 1 && y > 0 && y < c.ny - 1 && z > 0 && z < c.nz - 1;
+// A node of the node-parallel kernels and its place at the grid's faces.
+// The kernels run one grid row (y, z) per blockIdx.x and x across
+// blockIdx.y * blockDim.x + threadIdx.x, so y, z and their face flags are
+// uniform and only x is per lane; neighbour and pull offsets are then formed
+// from compile-time e_i without branches or per-lane division.
+struct Node3 {
+  int x;
+  unsigned idx;
+  bool x0, x1, y0, y1, z0, z1;  // x == 0, x == nx - 1, ...
+  __device__ __forceinline__ Node3(const CaseDev& c, int xx, int row) : x(xx) {
+    const int y = row % c.ny, z = row / c.ny;
+    idx = (unsigned)x + (unsigned)c.nx * (unsigned)row;
+    x0 = x == 0;
+    x1 = x == c.nx - 1;
+    y0 = y == 0;
+    y1 = y == c.ny - 1;
+    z0 = z == 0;
+    z1 = z == c.nz - 1;
+  }
+};
+
+// Offset, along one axis of pitch `pitch` and n nodes, of the stencil
+// neighbour one step s in {-1, 0, 1} away: the next node; across a periodic
+// seam its image; across a wall the mirror ghost, which is the node itself.
+__device__ __forceinline__ int face_step(int s, bool lo, bool hi, int wall, int n, int pitch) {
+  if (s == 0) return 0;
+  const bool out = s > 0 ? hi : lo;
+  return out ? (wall ? 0 : -s * (n - 1) * pitch) : s * pitch;
 }
 
-// Byte offset of the population of direction i pulled by node idx.
+// Node of the stencil neighbour x + e_i.
+__device__ __forceinline__ unsigned nbr3(const CaseDev& c, const Node3& nd, int i) {
+  return nd.idx + face_step(EX(i), nd.x0, nd.x1, c.wall_x, c.nx, 1) +
+         face_step(EY(i), nd.y0, nd.y1, c.wall_y, c.ny, c.nx) +
+         face_step(EZ(i), nd.z0, nd.z1, c.wall_z, c.nz, c.nx * c.ny);
+}
+
+// Offset of the pull source x - s along one axis: the previous node, across a
+// periodic seam its image; across a wall the node itself, and bb is set (the
+// population is then read in the opposite direction: halfway bounce-back).
+__device__ __forceinline__ int pull_step(int s, bool lo, bool hi, int wall, int n, int pitch,
+                                         bool& bb) {
+  if (s == 0) return 0;
+  const bool out = s > 0 ? lo : hi;
+  bb = bb || (out && wall);
+  return out ? (wall ? 0 : s * (n - 1) * pitch) : -s * pitch;
+}
+
+// Byte offset of the population of direction i pulled by the node.
 template <int S, bool G>
-__device__ __forceinline__ unsigned pull3(const CaseDev& c, int x, int y, int z, unsigned idx,
-                                          int i, bool interior) {
+__device__ __forceinline__ unsigned pull3(const CaseDev& c, const Node3& nd, int i) {
   using P = Pops<S, Q>;
-  if (i == 0) return G ? P::gofs(c, 0, idx) : P::fofs(c, 0, idx);
-  unsigned j;
+  if (i == 0) return G ? P::gofs(c, 0, nd.idx) : P::fofs(c, 0, nd.idx);
   bool bb = false;
-  if (interior) j = idx - EX(i) - c.nx * (EY(i) + c.ny * EZ(i));
-  else j = pull_src(c, x, y, z, EX(i), EY(i), EZ(i), &bb);
-  if (G) return bb ? P::gofs(c, OPP(i), idx) : P::gofs(c, i, j);
-  return bb ? P::fofs(c, OPP(i), idx) : P::fofs(c, i, j);
+  const int d = pull_step(EX(i), nd.x0, nd.x1, c.wall_x, c.nx, 1, bb) +
+                pull_step(EY(i), nd.y0, nd.y1, c.wall_y, c.ny, c.nx, bb) +
+                pull_step(EZ(i), nd.z0, nd.z1, c.wall_z, c.nz, c.nx * c.ny, bb);
+  const unsigned j = nd.idx + d;
+  if (G) return bb ? P::gofs(c, OPP(i), nd.idx) : P::gofs(c, i, j);
+  return bb ? P::fofs(c, OPP(i), nd.idx) : P::fofs(c, i, j);
+}
+
+// A staging coordinate g of a tile plus its halo mapped into the grid: the
+// periodic image or the wall mirror, then clamped.  Positions a real node
+// reads lie at most 2 <= n outside the grid, where one fold is exact; farther
+// ones occur only in the unused part of a ragged tile.
+__device__ __forceinline__ int fold3(int g, int n, int wall) {
+  if (g < 0) g = wall ? -g - 1 : g + n;
+  else if (g >= n) g = wall ? 2 * n - 1 - g : g - n;
+  return min(max(g, 0), n - 1);
+}
+
+// Launch shape of the node-parallel kernels (see Node3).
+struct RowGrid {
+  dim3 grid, block;
+};
+inline RowGrid row_grid(const CaseDev& c) {
+  const int bx = c.nx >= 256 ? 256 : ((c.nx + 63) / 64) * 64;
+  return {dim3(c.ny * c.nz, (c.nx + bx - 1) / bx), dim3(bx)};
 }
 
 struct Fields3 {
@@ -62,21 +125,20 @@ struct Fields3 {
 template <int S>
 __global__ void __launch_bounds__(256) k3_pull(CaseDev c, int parity, Fields3 fl) {
   using P = Pops<S, Q>;
-  const unsigned idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (unsigned)c.n) return;
-  int x, y, z;
-  coords(c, idx, x, y, z);
-  const bool in = is_interior(c, x, y, z);
+  const int x = blockIdx.y * blockDim.x + threadIdx.x;
+  if (x >= c.nx) return;
+  const Node3 nd(c, x, blockIdx.x);
+  const unsigned idx = nd.idx;
   const char* src = parity ? c.state[1] : c.state[0];
   float sm = 0.0f;
 #pragma unroll
-  for (int i = 1; i < Q; ++i) sm += P::f(c, src, i, pull3<S, false>(c, x, y, z, idx, i, in));
+  for (int i = 1; i < Q; ++i) sm += P::f(c, src, i, pull3<S, false>(c, nd, i));
   float hi, lo;
   two_sum(P::f(c, src, 0, P::fofs(c, 0, idx)), P::f0lo(c, src, idx) + sm, hi, lo);
   float m0 = 0.0f, mx = 0.0f, my = 0.0f, mz = 0.0f;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    const float v = P::g(c, src, pull3<S, true>(c, x, y, z, idx, i, in), WT(i));
+    const float v = P::g(c, src, pull3<S, true>(c, nd, i), WT(i));
     m0 += v;
     if (EX(i)) mx += EX(i) > 0 ? v : -v;
     if (EY(i)) my += EY(i) > 0 ? v : -v;
@@ -92,13 +154,13 @@ __global__ void __launch_bounds__(256) k3_pull(CaseDev c, int parity, Fields3 fl
 
 // Isotropic gradient 3 sum_i w_i e_i f_i of a node field, from differences
 // to the centre (the stencil of the step's grad p).
-__device__ __forceinline__ void grad_f(const CaseDev& c, const float* f, int x, int y, int z,
-                                       unsigned idx, bool in, float* g) {
-  const float f0 = f[idx];
+__device__ __forceinline__ void grad_f(const CaseDev& c, const float* f, const Node3& nd,
+                                       float* g) {
+  const float f0 = f[nd.idx];
   float ax = 0.0f, ay = 0.0f, az = 0.0f;
 #pragma unroll
   for (int i = 1; i < Q; ++i) {
-    const float d = f[nbr(c, x, y, z, i, in, idx)] - f0;
+    const float d = f[nbr3(c, nd, i)] - f0;
     const float w = i <= 6 ? (1.0f / 6.0f) : (1.0f / 12.0f);
     if (EX(i)) ax += EX(i) > 0 ? w * d : -w * d;
     if (EY(i)) ay += EY(i) > 0 ? w * d : -w * d;
@@ -174,9 +236,9 @@ k3_fields_t(CaseDev c, Fields3 fl, int want_lmu, int parity) {
       const int px = k % PX, py = (k / PX) % PY, pz = k / (PX * PY);
       int qx = x0 - 2 + px, qy = y0 - 2 + py, qz = z0 - 2 + pz;
       if (!inner) {
-        qx = map_axis(qx, c.nx, c.wall_x);
-        qy = map_axis(qy, c.ny, c.wall_y);
-        qz = map_axis(qz, c.nz, c.wall_z);
+        qx = fold3(qx, c.nx, c.wall_x);
+        qy = fold3(qy, c.ny, c.wall_y);
+        qz = fold3(qz, c.nz, c.wall_z);
       }
       const unsigned q = qx + c.nx * (qy + c.ny * qz);
       hv[it] = fl.phh[q];
@@ -228,9 +290,9 @@ k3_fields_t(CaseDev c, Fields3 fl, int want_lmu, int parity) {
         mx = mirror_local(mx, x0 - 1, c.nx, c.wall_x, MX);
         my = mirror_local(my, y0 - 1, c.ny, c.wall_y, MY);
         mz = mirror_local(mz, z0 - 1, c.nz, c.wall_z, T::MZ);
-        qx = map_axis(qx, c.nx, c.wall_x);
-        qy = map_axis(qy, c.ny, c.wall_y);
-        qz = map_axis(qz, c.nz, c.wall_z);
+        qx = fold3(qx, c.nx, c.wall_x);
+        qy = fold3(qy, c.ny, c.wall_y);
+        qz = fold3(qz, c.nz, c.wall_z);
       }
       const unsigned q = qx + c.nx * (qy + c.ny * qz);
       const int pc = (mx + 1) + PX * ((my + 1) + PY * (mz + 1));
@@ -385,30 +447,29 @@ __device__ __forceinline__ void collide_node(const CaseDev& c, const OutPtrs<S, 
 }
 
 template <int S>
-__device__ __forceinline__ void pull_node(const CaseDev& c, const char* src, int x, int y, int z,
-                                          unsigned idx, bool in, float* fv, float* gv) {
+__device__ __forceinline__ void pull_node(const CaseDev& c, const char* src, const Node3& nd,
+                                          float* fv, float* gv) {
   using P = Pops<S, Q>;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    if (i > 0) fv[i] = P::f(c, src, i, pull3<S, false>(c, x, y, z, idx, i, in));
-    gv[i] = P::g(c, src, pull3<S, true>(c, x, y, z, idx, i, in), WT(i));
+    if (i > 0) fv[i] = P::f(c, src, i, pull3<S, false>(c, nd, i));
+    gv[i] = P::g(c, src, pull3<S, true>(c, nd, i), WT(i));
   }
 }
 
 template <int S>
 __global__ void __launch_bounds__(256) k3_collide(CaseDev c, int parity, Fields3 fl) {
-  const unsigned idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (unsigned)c.n) return;
-  int x, y, z;
-  coords(c, idx, x, y, z);
-  const bool in = is_interior(c, x, y, z);
+  const int x = blockIdx.y * blockDim.x + threadIdx.x;
+  if (x >= c.nx) return;
+  const Node3 nd(c, x, blockIdx.x);
+  const unsigned idx = nd.idx;
   const char* src = parity ? c.state[1] : c.state[0];
   char* dst = parity ? c.state[0] : c.state[1];
   const OutPtrs<S, Q> op(c, dst);
   float fv[Q], gv[Q];
-  pull_node<S>(c, src, x, y, z, idx, in, fv, gv);
+  pull_node<S>(c, src, nd, fv, gv);
   float gp[3];
-  grad_f(c, fl.p, x, y, z, idx, in, gp);
+  grad_f(c, fl.p, nd, gp);
   NodeFields n;
   n.phh = fl.phh[idx];
   n.phl = fl.phl[idx];
@@ -546,8 +607,9 @@ void launch_fields_t(const CaseDev& c, const d3q19::Fields3& fl, int want_lmu, i
 template <int S>
 hipError_t pipeline(int variant, const CaseDev& c, int parity, const d3q19::Fields3& fl,
                     int want_lmu, bool collide, hipStream_t s) {
-  const int grid = (c.n + 255) / 256;
-  hipLaunchKernelGGL(d3q19::k3_pull<S>, dim3(grid), dim3(256), 0, s, c, parity, fl);
+  const d3q19::RowGrid rg = d3q19::row_grid(c);
+  if (rg.grid.y > 65535u) return hipErrorInvalidConfiguration;
+  hipLaunchKernelGGL(d3q19::k3_pull<S>, rg.grid, rg.block, 0, s, c, parity, fl);
   switch (variant) {
     case 0: launch_fields_t<16, 8, 4>(c, fl, want_lmu, parity, s); break;
     case 1: launch_fields_t<32, 4, 4>(c, fl, want_lmu, parity, s); break;
@@ -556,7 +618,7 @@ hipError_t pipeline(int variant, const CaseDev& c, int parity, const d3q19::Fiel
     case 4: launch_fields_t<8, 8, 8>(c, fl, want_lmu, parity, s); break;
     default: return hipErrorInvalidValue;
   }
-  if (collide) hipLaunchKernelGGL(d3q19::k3_collide<S>, dim3(grid), dim3(256), 0, s, c, parity, fl);
+  if (collide) hipLaunchKernelGGL(d3q19::k3_collide<S>, rg.grid, rg.block, 0, s, c, parity, fl);
   return hipGetLastError();
 }
 }  // namespace

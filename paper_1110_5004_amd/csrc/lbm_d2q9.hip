@@ -884,15 +884,17 @@ hipError_t launch_step_t(const LaunchArgs& a) {
   return hipGetLastError();
 }
 
-template <int TX, int TY, int S>
+template <int TX, int TY, int NPT, int WPE, int S>
 hipError_t launch_fields_t(const LaunchArgs& a, const FieldPtrs& f) {
   FieldOut fo{f.phi, f.u[0], f.u[1], f.u[2], f.p, f.mu, f.fa[0], f.fa[1], f.fa[2]};
   if (a.rf == 2)
-    hipLaunchKernelGGL((d2q9::k_tile<TX, TY, 1, 2, S, true, 0>), dim3(a.grid), dim3(TX * TY),
-                       0, a.stream, a.cases, a.tiles, a.ntiles, a.parity, fo);
+    hipLaunchKernelGGL((d2q9::k_tile<TX, TY, NPT, 2, S, true, WPE>), dim3(a.grid),
+                       dim3(TX * TY / NPT), 0, a.stream, a.cases, a.tiles, a.ntiles, a.parity,
+                       fo);
   else
-    hipLaunchKernelGGL((d2q9::k_tile<TX, TY, 1, 1, S, true, 0>), dim3(a.grid), dim3(TX * TY),
-                       0, a.stream, a.cases, a.tiles, a.ntiles, a.parity, fo);
+    hipLaunchKernelGGL((d2q9::k_tile<TX, TY, NPT, 1, S, true, WPE>), dim3(a.grid),
+                       dim3(TX * TY / NPT), 0, a.stream, a.cases, a.tiles, a.ntiles, a.parity,
+                       fo);
   return hipGetLastError();
 }
 
@@ -948,12 +950,15 @@ hipError_t d2q9_step(int variant, const LaunchArgs& a) {
   }
 }
 
-// The field dump uses the shape of variant 0.
+// The field dump: 64 x 16 tiles, two nodes per thread (the shape of the
+// step's variant 2).
+const TileShape kD2Q9FieldShape = {64, 16, 1, 512, 0};
+
 hipError_t d2q9_fields(const LaunchArgs& a, const FieldPtrs& f) {
   switch (a.storage) {
-    case ST_FP32: return launch_fields_t<32, 16, ST_FP32>(a, f);
-    case ST_FP16: return launch_fields_t<32, 16, ST_FP16>(a, f);
-    default: return launch_fields_t<32, 16, ST_BF16>(a, f);
+    case ST_FP32: return launch_fields_t<64, 16, 2, 4, ST_FP32>(a, f);
+    case ST_FP16: return launch_fields_t<64, 16, 2, 4, ST_FP16>(a, f);
+    default: return launch_fields_t<64, 16, 2, 4, ST_BF16>(a, f);
   }
 }
 

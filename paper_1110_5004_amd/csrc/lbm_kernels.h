@@ -35,6 +35,7 @@ struct FieldPtrs {
 };
 
 extern const TileShape kD2Q9Tiles[];
+extern const TileShape kD2Q9FieldShape;  // tile of the D2Q9 field dump
 extern const int kD2Q9TileCount;
 extern const TileShape kD3Q19Tiles[];
 extern const int kD3Q19TileCount;

@@ -153,7 +153,7 @@ std::vector<TileDev> build_tiles(const lbm_case_params* cs, int n, const lbm::Ti
 // Field-dump tile shape: variant 0 of each lattice.
 const lbm::TileShape& field_shape(int lattice) {
   int n;
-  return tiles_for(lattice, &n)[0];
+  return lattice == LBM_D2Q9 ? lbm::kD2Q9FieldShape : tiles_for(lattice, &n)[0];
 }
 
 struct Layout {

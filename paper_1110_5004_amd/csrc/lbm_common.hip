@@ -1,6 +1,8 @@
 // lbm_common.hip -- lattice-independent gfx950 kernels: streaming of raw
 // words (the exact pull permutation of the step), 16-bit encoding, the
-// bandwidth-calibration copy, and the fixed-order FP64 diagnostics reduction.
+// bandwidth-calibration copies, the paper-experiment diagnostics (spread
+// radius, F_a from discrete data and in Lee and Lin's form), and the
+// fixed-order FP64 diagnostics reduction.
 #include "lbm_dev.h"
 #include "lbm_kernels.h"
 #include "lbm_lattice.h"

@@ -11,6 +11,10 @@
 //      the paragraph after it); u, p -> LDS
 //   D  over the tile: grad p -> grad psi, BGK collision of f (order
 //      parameter) and of gbar with the forcing of Eq. 8, store.
+// With the correction from data (RF = 2) phase C first forms the uncorrected
+// rho u over the tile plus 2, then the rate (rho^n - rho^(n-1)) + div(rho u)
+// over the tile plus 1 as the coefficient of -F_a; phi^(n-1) comes from a
+// plane that every state copy carries.
 // Stencil positions beyond a wall hold the values of their mirror node
 // (halfway bounce-back walls, neutral wetting); positions beyond a periodic
 // seam hold the wrapped node.  Every per-node quantity is a function of the
@@ -759,6 +763,7 @@ __device__ __forceinline__ void tile_bcd(TileLds<TX, TY, RF>& L, const CaseDev& 
 }
 
 // RF = 1: lap mu is formed (corrected model, or the F_a dump); phi halo 3.
+// RF = 2: the correction from data (phases C1, C2); phi halo 3.
 // WPE > 0 asks the compiler for at least that many waves per SIMD (fewer
 // registers, more tiles in flight per CU).
 //

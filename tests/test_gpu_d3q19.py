@@ -111,3 +111,29 @@ def test_splash3d_full_size(hip):
     d16 = s16.diagnostics()
     print(f"splash3d fp16 300 steps: drift {d16['mass_drift_rel']:.2e} umax {d16['umax']:.4f}")
     assert d16["nonfinite"] == 0 and d16["mass_drift_rel"] <= 1e-6
+
+
+def test_splash3d_fp16_against_fp32_5000_steps(hip):
+    """The D3Q19 splash (256x256x128) for 5000 steps in FP16 storage, with
+    FP32 storage as the reference: mass drift, droplet centroid and centroid
+    velocity of the two runs (the FP16-storage bounds: velocity within 1 %,
+    drift <= 1e-6), max|dphi| printed."""
+    case = W.splash_3d(remove_fa=1)
+    out = {}
+    for st in ("fp32", "fp16"):
+        sim = hip.Simulation([case], storage=st)
+        sim.step(5000)
+        d = sim.diagnostics()
+        out[st] = (d, sim.moments()["phi"].astype(np.float64))
+        sim.close()
+    (d32, p32), (d16, p16) = out["fp32"], out["fp16"]
+    dv = np.abs(np.asarray(d16["centroid_vel"]) - np.asarray(d32["centroid_vel"]))
+    vscale = np.abs(np.asarray(d32["centroid_vel"])).max()
+    dc = np.abs(np.asarray(d16["centroid"]) - np.asarray(d32["centroid"])).max()
+    dphi = float(np.abs(p16 - p32).max())
+    print(f"splash3d 5000 steps fp16 vs fp32: centroid {dc:.3e} l.u., centroid velocity "
+          f"{dv.max() / vscale:.3e} relative, max|dphi| {dphi:.3e}, drift fp32 "
+          f"{d32['mass_drift_rel']:.2e} fp16 {d16['mass_drift_rel']:.2e}")
+    assert d32["nonfinite"] == 0 and d16["nonfinite"] == 0
+    assert d32["mass_drift_rel"] <= 1e-6 and d16["mass_drift_rel"] <= 1e-6
+    assert dv.max() <= 0.01 * vscale

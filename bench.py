@@ -96,13 +96,24 @@ def leg(torch, W, hip, storage, remove_fa, steps, warmup, workload="splash1024x5
                 umax=d["umax"], variant=variant_used)
 
 
-def leg_3d(torch, W, hip, storage, remove_fa, steps=100, warmup=10):
-    """D3Q19 splash 256x256x128 (periodic x, y, walls z)."""
+def kernel_3d(hip, variant):
+    """Name of the D3Q19 step a variant launches: the fused step (an x-y tile
+    marching up a z chunk of 16 or more planes) or the three-kernel step."""
+    if hip.variants(hip.D3Q19)[variant][2] >= 16:
+        return "k3_slab (fused D3Q19 step)"
+    return "k3_pull + k3_fields_t + k3_collide"
+
+
+def leg_3d(torch, W, hip, storage, remove_fa, steps=100, warmup=10, variant=-1):
+    """D3Q19 splash 256x256x128 (periodic x, y, walls z); variant -1: autotuned."""
     from paper_1110_5004_amd import tune
     case = W.splash_3d(remove_fa=remove_fa)
-    probe = hip.Simulation([case], storage=storage)
-    rec = tune.tune(probe, steps=10)
-    probe.close()
+    if variant >= 0:
+        rec = dict(variant=variant, grid=0, graph_steps=16)
+    else:
+        probe = hip.Simulation([case], storage=storage)
+        rec = tune.tune(probe, steps=10)
+        probe.close()
     sim = hip.Simulation([case], storage=storage)
     sim.set_launch(rec["variant"], rec["grid"], rec["graph_steps"])
     t = time_gpu(torch, sim, steps, warmup)
@@ -114,7 +125,8 @@ def leg_3d(torch, W, hip, storage, remove_fa, steps=100, warmup=10):
     return dict(mlups=round(mlups, 1), achieved_gbs=round(ach, 1),
                 frac=round(ach / HBM_PEAK_GBS, 4), bytes_per_lu=BYTES_PER_LU_3D[storage],
                 steps=steps, nonfinite=int(d["nonfinite"]), mass_drift_rel=d["mass_drift_rel"],
-                ms_per_step=round(1e3 * t / steps, 4), variant=variant)
+                ms_per_step=round(1e3 * t / steps, 4), variant=variant,
+                kernel=kernel_3d(hip, variant))
 
 
 def leg_ensemble(torch, W, hip, storage, steps=200, warmup=20):
@@ -326,7 +338,7 @@ def traffic_for(kernel_key, seconds_per_launch):
 
 def main_3d(a, torch, W, hip):
     """The D3Q19 256x256x128 splash alone (profiling of the 3-D path)."""
-    r = leg_3d(torch, W, hip, a.storage, a.remove_fa, a.steps, a.warmup)
+    r = leg_3d(torch, W, hip, a.storage, a.remove_fa, a.steps, a.warmup, a.variant)
     pc_s = pull_copy_ceiling(torch, hip, hip.D3Q19, a.storage, (256, 256, 128), reps=20)
     step_s = r["ms_per_step"] / 1e3
     print(json.dumps({
@@ -342,7 +354,7 @@ def main_3d(a, torch, W, hip):
         "roofline": {"bound": "hbm", "achieved": r["achieved_gbs"], "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": r["frac"], "traffic": None,
                      "bytes_per_lu": r["bytes_per_lu"],
-                     "kernel": "k3_pull + k3_fields_t + k3_collide", "variant": r["variant"],
+                     "kernel": r["kernel"], "variant": r["variant"],
                      "pull_copy_us": round(pc_s * 1e6, 2),
                      "frac_of_pull_copy": round(pc_s / step_s, 4)},
         "check": {"mass_drift_rel": r["mass_drift_rel"], "nonfinite": r["nonfinite"]},

@@ -42,9 +42,10 @@ struct Node3 {
   int x;
   unsigned idx;
   bool x0, x1, y0, y1, z0, z1;  // x == 0, x == nx - 1, ...
-  __device__ __forceinline__ Node3(const CaseDev& c, int xx, int row) : x(xx) {
-    const int y = row % c.ny, z = row / c.ny;
-    idx = (unsigned)x + (unsigned)c.nx * (unsigned)row;
+  __device__ __forceinline__ Node3(const CaseDev& c, int xx, int row)
+      : Node3(c, xx, row % c.ny, row / c.ny) {}
+  __device__ __forceinline__ Node3(const CaseDev& c, int xx, int y, int z) : x(xx) {
+    idx = (unsigned)x + (unsigned)c.nx * ((unsigned)y + (unsigned)c.ny * (unsigned)z);
     x0 = x == 0;
     x1 = x == c.nx - 1;
     y0 = y == 0;
@@ -82,8 +83,8 @@ __device__ __forceinline__ int pull_step(int s, bool lo, bool hi, int wall, int 
 }
 
 // Byte offset of the population of direction i pulled by the node.
-template <int S, bool G>
-__device__ __forceinline__ unsigned pull3(const CaseDev& c, const Node3& nd, int i) {
+template <int S, bool G, class N>
+__device__ __forceinline__ unsigned pull3(const CaseDev& c, const N& nd, int i) {
   using P = Pops<S, Q>;
   if (i == 0) return G ? P::gofs(c, 0, nd.idx) : P::fofs(c, 0, nd.idx);
   bool bb = false;
@@ -121,29 +122,46 @@ struct Fields3 {
   float* dd;  // correction from data: the rate D of -F_a = D u
 };
 
-// ---- 1: pull, phi, moments
-template <int S>
-__global__ void __launch_bounds__(256) k3_pull(CaseDev c, int parity, Fields3 fl) {
+// phi = sum_i f_i of the pulled populations (Eq. 4a's zeroth moment), as a
+// float-float pair: f_0 (high and low part) plus the sum of the others.
+template <int S, class N>
+__device__ __forceinline__ void pull_phi(const CaseDev& c, const char* src, const N& nd,
+                                         float& hi, float& lo) {
   using P = Pops<S, Q>;
-  const int x = blockIdx.y * blockDim.x + threadIdx.x;
-  if (x >= c.nx) return;
-  const Node3 nd(c, x, blockIdx.x);
-  const unsigned idx = nd.idx;
-  const char* src = parity ? c.state[1] : c.state[0];
   float sm = 0.0f;
 #pragma unroll
-  for (int i = 1; i < Q; ++i) sm += P::f(c, src, i, pull3<S, false>(c, nd, i));
-  float hi, lo;
-  two_sum(P::f(c, src, 0, P::fofs(c, 0, idx)), P::f0lo(c, src, idx) + sm, hi, lo);
-  float m0 = 0.0f, mx = 0.0f, my = 0.0f, mz = 0.0f;
+  for (int i = 1; i < Q; ++i) sm += P::f(c, src, i, pull3<S, false, N>(c, nd, i));
+  two_sum(P::f(c, src, 0, P::fofs(c, 0, nd.idx)), P::f0lo(c, src, nd.idx) + sm, hi, lo);
+}
+
+// Zeroth and first moments of the pulled gbar (the inputs of the recovery of
+// p and u).
+template <int S, class N>
+__device__ __forceinline__ void pull_moments(const CaseDev& c, const char* src, const N& nd,
+                                             float& m0, float& mx, float& my, float& mz) {
+  using P = Pops<S, Q>;
+  m0 = mx = my = mz = 0.0f;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    const float v = P::g(c, src, pull3<S, true>(c, nd, i), WT(i));
+    const float v = P::g(c, src, pull3<S, true, N>(c, nd, i), WT(i));
     m0 += v;
     if (EX(i)) mx += EX(i) > 0 ? v : -v;
     if (EY(i)) my += EY(i) > 0 ? v : -v;
     if (EZ(i)) mz += EZ(i) > 0 ? v : -v;
   }
+}
+
+// ---- 1: pull, phi, moments
+template <int S>
+__global__ void __launch_bounds__(256) k3_pull(CaseDev c, int parity, Fields3 fl) {
+  const int x = blockIdx.y * blockDim.x + threadIdx.x;
+  if (x >= c.nx) return;
+  const Node3 nd(c, x, blockIdx.x);
+  const unsigned idx = nd.idx;
+  const char* src = parity ? c.state[1] : c.state[0];
+  float hi, lo, m0, mx, my, mz;
+  pull_phi<S>(c, src, nd, hi, lo);
+  pull_moments<S>(c, src, nd, m0, mx, my, mz);
   fl.phh[idx] = hi;
   fl.phl[idx] = lo;
   fl.m0[idx] = m0;
@@ -392,8 +410,38 @@ struct NodeFields {
 // (see the D2Q9 step):
 //   g* = (1 - om) g + w [A + B_i + t_i (C + D_i)],  f* = (1 - om_f) f + w (P + Q t_i)
 // and the stores of node idx.  fv[1..18], gv[0..18]: its pulled populations.
+// Destination of the stores by the copy's base address alone (each store forms
+// its plane offset), for kernels short of scalar registers; the same stores as
+// OutPtrs.
 template <int S>
-__device__ __forceinline__ void collide_node(const CaseDev& c, const OutPtrs<S, Q>& op,
+struct BaseOut {
+  char* base;
+  __device__ __forceinline__ float put_f(const CaseDev& c, int i, unsigned idx, float v) const {
+    return Pops<S, Q>::put_f(c, base, i, idx, v);
+  }
+  __device__ __forceinline__ void put_g(const CaseDev& c, int i, unsigned idx, float v,
+                                        float wi) const {
+    Pops<S, Q>::put_g(c, base, i, idx, v, wi);
+  }
+  __device__ __forceinline__ void put_f0(const CaseDev& c, unsigned idx, float hi,
+                                         float lo) const {
+    Pops<S, Q>::put_f0(c, base, idx, hi, lo);
+  }
+};
+
+template <int S>
+__device__ __forceinline__ void put_f0(const CaseDev&, const OutPtrs<S, Q>& op, unsigned idx,
+                                       float hi, float lo) {
+  op.put_f0(idx, hi, lo);
+}
+template <int S>
+__device__ __forceinline__ void put_f0(const CaseDev& c, const BaseOut<S>& op, unsigned idx,
+                                       float hi, float lo) {
+  op.put_f0(c, idx, hi, lo);
+}
+
+template <int S, class Out>
+__device__ __forceinline__ void collide_node(const CaseDev& c, const Out& op,
                                              unsigned idx, const float* fv, const float* gv,
                                              const NodeFields& n) {
   const float ph = n.phh + n.phl;
@@ -443,18 +491,44 @@ __device__ __forceinline__ void collide_node(const CaseDev& c, const OutPtrs<S, 
   }
   float h0, e0;
   two_sum(n.phh, -fsum, h0, e0);
-  op.put_f0(idx, h0, e0 + n.phl);
+  put_f0<S>(c, op, idx, h0, e0 + n.phl);
 }
 
 template <int S>
 __device__ __forceinline__ void pull_node(const CaseDev& c, const char* src, const Node3& nd,
                                           float* fv, float* gv) {
+  using N = Node3;
   using P = Pops<S, Q>;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    if (i > 0) fv[i] = P::f(c, src, i, pull3<S, false>(c, nd, i));
-    gv[i] = P::g(c, src, pull3<S, true>(c, nd, i), WT(i));
+    if (i > 0) fv[i] = P::f(c, src, i, pull3<S, false, N>(c, nd, i));
+    gv[i] = P::g(c, src, pull3<S, true, N>(c, nd, i), WT(i));
   }
+}
+
+// The pulled f_1..f_18 of a node, and its phi from them as pull_phi forms it.
+template <int S, class N>
+__device__ __forceinline__ void pull_f(const CaseDev& c, const char* src, const N& nd,
+                                       float* fv) {
+  using P = Pops<S, Q>;
+#pragma unroll
+  for (int i = 1; i < Q; ++i) fv[i] = P::f(c, src, i, pull3<S, false, N>(c, nd, i));
+}
+template <int S, class N>
+__device__ __forceinline__ void phi_of(const CaseDev& c, const char* src, const N& nd,
+                                       const float* fv, float& hi, float& lo) {
+  using P = Pops<S, Q>;
+  float sm = 0.0f;
+#pragma unroll
+  for (int i = 1; i < Q; ++i) sm += fv[i];
+  two_sum(P::f(c, src, 0, P::fofs(c, 0, nd.idx)), P::f0lo(c, src, nd.idx) + sm, hi, lo);
+}
+template <int S, class N>
+__device__ __forceinline__ void pull_g(const CaseDev& c, const char* src, const N& nd,
+                                       float* gv) {
+  using P = Pops<S, Q>;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) gv[i] = P::g(c, src, pull3<S, true, N>(c, nd, i), WT(i));
 }
 
 template <int S>
@@ -488,6 +562,283 @@ __global__ void __launch_bounds__(256) k3_collide(CaseDev c, int parity, Fields3
   collide_node<S>(c, op, idx, fv, gv, n);
   // correction from data: the copy carries this step's phi
   if (c.phiv) gstore<float>(dst, c.phiv + 4u * idx, n.phh + n.phl);
+}
+
+// ---- fused step: one x-y tile of the grid marching up a chunk of z planes
+//
+// A workgroup owns a TX x TY tile of the x-y plane and the planes [za, zb) of
+// one z chunk.  It keeps rings of planes in LDS:
+//   phi (float-float) over the tile + 3, 4 planes  (summed from pulled f)
+//   mu over the tile + 2, 3 planes
+//   p over the tile + 1, 3 planes
+// and iteration z stages phi(z + 3), forms mu(z + 2), pulls the gbar moments
+// and forms u and p at z + 1 (the tile's own nodes keep u, grad phi, mu and the
+// correction coefficient in registers), then collides plane z.  Populations
+// come from HBM once: the halo positions and the second read by the collision
+// are L2 hits, and no field plane goes through HBM.
+//
+// Positions beyond a wall: phi is staged from the mirror node (periodic image
+// on periodic axes); in the x-y plane mu, u and p at such a position are
+// formed around the mirror position, so they equal the mirror node's values;
+// along z the planes beyond a wall are not formed and their reads go to the
+// mirror plane (a halfway wall mirrors the plane next to it).  Every quantity
+// is the same expression, in the same order, as in the three-kernel step, so
+// the two give the same bits.  The correction from data takes the
+// three-kernel step (it needs rho u_o over the tile + 1 of the previous
+// recovery).
+template <int TX, int TY>
+struct SlabLds {
+  static constexpr int PX = TX + 6, PY = TY + 6, NP = PX * PY;  // phi plane
+  static constexpr int MX = TX + 4, MY = TY + 4, NM = MX * MY;  // mu plane
+  static constexpr int UX = TX + 2, UY = TY + 2, NU = UX * UY;  // p plane
+  float ph[4][NP];
+  float pl[4][NP];
+  float mu[3][NM];
+  float p[3][NU];
+};
+
+// Ring slot of plane k (k >= -6).
+__device__ __forceinline__ int slot4(int k) { return (k + 8) & 3; }
+__device__ __forceinline__ int slot3(int k) { return (k + 6) % 3; }
+
+// The plane whose mu / p a read of plane k takes: k itself, or across a wall
+// along z the mirror plane.
+__device__ __forceinline__ int zread(const CaseDev& c, int k) {
+  return c.wall_z ? min(max(k, 0), c.nz - 1) : k;
+}
+
+// mu = theta'(phi) - kappa lap phi at position pc of a phi plane of row pitch
+// PX; bm, b0, bp: offsets of the planes below, at and above.
+template <int PX>
+__device__ __forceinline__ float slab_mu(const CaseDev& c, const float* ph, const float* pl,
+                                         int bm, int b0, int bp, int pc) {
+  const float h0 = ph[b0 + pc], l0 = pl[b0 + pc];
+  float la = 0.0f, le = 0.0f;
+#pragma unroll
+  for (int i = 1; i < Q; ++i) {
+    const int j = (EZ(i) < 0 ? bm : (EZ(i) > 0 ? bp : b0)) + pc + EX(i) + PX * EY(i);
+    const float d = (ph[j] - h0) + (pl[j] - l0);
+    if (i <= 6) la += d;
+    else le += d;
+  }
+  const float lap = (1.0f / 3.0f) * la + (1.0f / 6.0f) * le;
+  return dtheta(c, h0, l0) - c.kappa * lap;
+}
+
+template <int S, int TX, int TY>
+__global__ void __launch_bounds__(TX * TY) k3_slab(CaseDev c, int parity, int zs) {
+  using T = SlabLds<TX, TY>;
+  constexpr int NT = TX * TY, PX = T::PX, MX = T::MX, UX = T::UX, UY = T::UY;
+  constexpr int NRING = T::NU - NT;  // positions of the tile + 1 outside the tile
+  __shared__ T L;
+  // XCD-aware tile order as in the fields kernel; x fastest, then y, then the
+  // z chunk, so an XCD's consecutive tiles share their x-y halos
+  const int ntx = (c.nx + TX - 1) / TX, nty = (c.ny + TY - 1) / TY;
+  const int ntiles = ntx * nty * ((c.nz + zs - 1) / zs);
+  const int chunk = (ntiles + 7) >> 3;
+  const int t = (blockIdx.x & 7) * chunk + (blockIdx.x >> 3);
+  if (blockIdx.x >= (unsigned)(8 * chunk) || t >= ntiles) return;
+  const int x0 = (t % ntx) * TX, y0 = ((t / ntx) % nty) * TY;
+  const int za = (t / (ntx * nty)) * zs, zb = min(za + zs, c.nz);
+  const int tid = threadIdx.x;
+  const bool inner = x0 >= 3 && x0 + TX + 3 <= c.nx && y0 >= 3 && y0 + TY + 3 <= c.ny;
+  const int lx = tid % TX, ly = tid / TX;
+  const int gx = x0 + lx, gy = y0 + ly;
+  const bool own = gx < c.nx && gy < c.ny;
+  const char* src = parity ? c.state[1] : c.state[0];
+  const BaseOut<S> op{parity ? c.state[0] : c.state[1]};
+  float* const php = &L.ph[0][0];
+  float* const plp = &L.pl[0][0];
+  float* const mup = &L.mu[0][0];
+  float* const pp = &L.p[0][0];
+
+  constexpr int PY = T::PY;
+  constexpr int NPRING = T::NP - NT;  // positions of the tile + 3 outside the tile
+  NodeFields cur{}, nxt{};  // own node: plane z (collided now), plane z + 1
+  // own node's pulled f_1..f_18 at planes z, z + 1, z + 2 and z + 3 (fn)
+  float fa[Q], fb[Q], fc[Q], fn[Q];
+  for (int z = za - 6; z < zb; ++z) {
+    // P: phi at plane z + 3 over the tile + 3: first each thread's own node,
+    // whose pulled f_1..f_18 it keeps for the collision of that plane three
+    // iterations later, then the 3-wide ring around the tile
+    {
+      const int k = z + 3;
+      const int qz = fold3(k, c.nz, c.wall_z);
+      const int b = slot4(k) * T::NP;
+      for (int r = tid - NT; r < NPRING; r += NT) {
+        int px, py;
+        if (r < 0) {
+          px = lx + 3;
+          py = ly + 3;
+        } else if (r < 3 * PX) {
+          px = r % PX;
+          py = r / PX;
+        } else if (r < 6 * PX) {
+          px = (r - 3 * PX) % PX;
+          py = PY - 3 + (r - 3 * PX) / PX;
+        } else {
+          const int q = r - 6 * PX, col = q % 6;
+          px = col < 3 ? col : PX - 6 + col;
+          py = 3 + q / 6;
+        }
+        int qx = x0 - 3 + px, qy = y0 - 3 + py;
+        if (!inner) {
+          qx = fold3(qx, c.nx, c.wall_x);
+          qy = fold3(qy, c.ny, c.wall_y);
+        }
+        const Node3 nd(c, qx, qy, qz);
+        float hv, lv;
+        if (r < 0) {
+          pull_f<S>(c, src, nd, fn);
+          phi_of<S>(c, src, nd, fn, hv, lv);
+        } else {
+          pull_phi<S>(c, src, nd, hv, lv);
+        }
+        php[b + px + PX * py] = hv;
+        plp[b + px + PX * py] = lv;
+      }
+    }
+    __syncthreads();
+
+    // M: mu at plane z + 2 over the tile + 2
+    {
+      const int k = z + 2;
+      if (k >= za - 2 && !(c.wall_z && (k < 0 || k >= c.nz))) {
+        const int bm = slot4(k - 1) * T::NP, b0 = slot4(k) * T::NP, bp = slot4(k + 1) * T::NP;
+        const int b = slot3(k) * T::NM;
+        for (int pos = tid; pos < T::NM; pos += NT) {
+          int mx = pos % MX, my = pos / MX;
+          if (!inner) {
+            mx = mirror_local(mx, x0 - 2, c.nx, c.wall_x, MX);
+            my = mirror_local(my, y0 - 2, c.ny, c.wall_y, T::MY);
+          }
+          mup[b + pos] = slab_mu<PX>(c, php, plp, bm, b0, bp, (mx + 1) + PX * (my + 1));
+        }
+      }
+    }
+    __syncthreads();
+
+    // U: gbar moments, grad phi, lap mu, u and p at plane z + 1 over the
+    // tile + 1; first each thread's own node, then the ring around the tile
+    {
+      const int k = z + 1;
+      if (k >= za - 1 && !(c.wall_z && (k < 0 || k >= c.nz))) {
+        const int qz = fold3(k, c.nz, c.wall_z);
+        const int bm = slot4(k - 1) * T::NP, b0 = slot4(k) * T::NP, bp = slot4(k + 1) * T::NP;
+        const int um = slot3(zread(c, k - 1)) * T::NM, u0 = slot3(k) * T::NM,
+                  up = slot3(zread(c, k + 1)) * T::NM;
+        const int pb = slot3(k) * T::NU;
+        for (int r = tid - NT; r < NRING; r += NT) {
+          // r < 0: the own node; else the r-th ring position
+          int ux, uy;
+          if (r < 0) {
+            ux = lx + 1;
+            uy = ly + 1;
+          } else if (r < UX) {
+            ux = r;
+            uy = 0;
+          } else if (r < 2 * UX) {
+            ux = r - UX;
+            uy = UY - 1;
+          } else {
+            ux = ((r - 2 * UX) & 1) ? UX - 1 : 0;
+            uy = 1 + ((r - 2 * UX) >> 1);
+          }
+          int qx = x0 - 1 + ux, qy = y0 - 1 + uy, mx = ux, my = uy;
+          if (!inner) {
+            mx = mirror_local(ux, x0 - 1, c.nx, c.wall_x, UX);
+            my = mirror_local(uy, y0 - 1, c.ny, c.wall_y, UY);
+            qx = fold3(qx, c.nx, c.wall_x);
+            qy = fold3(qy, c.ny, c.wall_y);
+          }
+          float m0, m1x, m1y, m1z;
+          pull_moments<S>(c, src, Node3(c, qx, qy, qz), m0, m1x, m1y, m1z);
+          const int pc = (mx + 2) + PX * (my + 2);
+          const int mc = (mx + 1) + MX * (my + 1);
+          const float h0 = php[b0 + pc], l0 = plp[b0 + pc];
+          float g[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+          for (int i = 1; i < Q; ++i) {
+            const int j = (EZ(i) < 0 ? bm : (EZ(i) > 0 ? bp : b0)) + pc + EX(i) + PX * EY(i);
+            const float d = (php[j] - h0) + (plp[j] - l0);
+            const float w = i <= 6 ? (1.0f / 6.0f) : (1.0f / 12.0f);  // 3 w_i
+            if (EX(i)) g[0] += EX(i) > 0 ? w * d : -w * d;
+            if (EY(i)) g[1] += EY(i) > 0 ? w * d : -w * d;
+            if (EZ(i)) g[2] += EZ(i) > 0 ? w * d : -w * d;
+          }
+          const float mu = mup[u0 + mc];
+          float lmu = 0.0f;
+          if (c.corr != 0.0f) {
+            float la = 0.0f, le = 0.0f;
+#pragma unroll
+            for (int i = 1; i < Q; ++i) {
+              const int j = (EZ(i) < 0 ? um : (EZ(i) > 0 ? up : u0)) + mc + EX(i) + MX * EY(i);
+              const float d = mup[j] - mu;
+              if (i <= 6) la += d;
+              else le += d;
+            }
+            lmu = (1.0f / 3.0f) * la + (1.0f / 6.0f) * le;
+          }
+          const float ph = h0 + l0;
+          const float rho = c.rho0 + ph * c.drho;
+          const float fsx = mu * g[0], fsy = mu * g[1];
+          const float fsz = mu * g[2] - (rho - c.rho_ref) * c.gravity;
+          const float cc = c.corr * lmu;
+          const float iden = __builtin_amdgcn_rcpf(rho - 0.5f * cc);
+          const float vx = (3.0f * m1x + 0.5f * fsx) * iden;
+          const float vy = (3.0f * m1y + 0.5f * fsy) * iden;
+          const float vz = (3.0f * m1z + 0.5f * fsz) * iden;
+          const float p = m0 + (1.0f / 6.0f) * c.drho * (vx * g[0] + vy * g[1] + vz * g[2]);
+          pp[pb + ux + UX * uy] = p;
+          if (r < 0) {
+            nxt.phh = h0;
+            nxt.phl = l0;
+            nxt.mu = mu;
+            nxt.cc = cc;
+            nxt.p = p;
+            nxt.ux = vx;
+            nxt.uy = vy;
+            nxt.uz = vz;
+            nxt.gx = g[0];
+            nxt.gy = g[1];
+            nxt.gz = g[2];
+          }
+        }
+      }
+    }
+    __syncthreads();
+
+    // C: grad p and the collision of the tile's nodes at plane z
+    if (z >= za && own) {
+      const Node3 nd(c, gx, gy, z);
+      float gv[Q];
+      pull_g<S>(c, src, nd, gv);
+      const int uc = (lx + 1) + UX * (ly + 1);
+      const int pm = slot3(zread(c, z - 1)) * T::NU, p0 = slot3(z) * T::NU,
+                pq = slot3(zread(c, z + 1)) * T::NU;
+      const float f0 = pp[p0 + uc];
+      float ax = 0.0f, ay = 0.0f, az = 0.0f;
+#pragma unroll
+      for (int i = 1; i < Q; ++i) {
+        const float d = pp[(EZ(i) < 0 ? pm : (EZ(i) > 0 ? pq : p0)) + uc + EX(i) + UX * EY(i)] - f0;
+        const float w = i <= 6 ? (1.0f / 6.0f) : (1.0f / 12.0f);
+        if (EX(i)) ax += EX(i) > 0 ? w * d : -w * d;
+        if (EY(i)) ay += EY(i) > 0 ? w * d : -w * d;
+        if (EZ(i)) az += EZ(i) > 0 ? w * d : -w * d;
+      }
+      cur.gpx = ax;
+      cur.gpy = ay;
+      cur.gpz = az;
+      collide_node<S>(c, op, nd.idx, fa, gv, cur);
+    }
+    cur = nxt;
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+      fa[i] = fb[i];
+      fb[i] = fc[i];
+      fc[i] = fn[i];
+    }
+  }
 }
 
 // ---- field dump for lbm_moments / diagnostics
@@ -564,10 +915,14 @@ k3_init(CaseDev c, int parity, const double* __restrict__ phi0, const double* __
 }  // namespace d3q19
 
 // ------------------------------------------------------------ launchers
-// Variants: the tile of the fields kernel (the pull and collision kernels are
-// node-parallel, 256 threads).  All give the same bits.
-const TileShape kD3Q19Tiles[] = {{16, 8, 4, 512, 0}, {32, 4, 4, 512, 0}, {32, 8, 2, 512, 0},
-                                 {16, 16, 2, 512, 0}, {8, 8, 8, 512, 0}};
+// Variants 0-4: the three-kernel step, by the tile of its fields kernel (the
+// pull and collision kernels are node-parallel, 256 threads).  Variants 5-8:
+// the fused step, by its x-y tile and z chunk (tz planes).  All give the same
+// bits; the correction from data always takes the three-kernel step (tile 1).
+const TileShape kD3Q19Tiles[] = {{16, 8, 4, 512, 0},  {32, 4, 4, 512, 0},  {32, 8, 2, 512, 0},
+                                 {16, 16, 2, 512, 0}, {8, 8, 8, 512, 0},   {32, 8, 16, 256, 0},
+                                 {32, 8, 32, 256, 0}, {32, 16, 16, 512, 0}, {32, 16, 32, 512, 0}};
+constexpr int kD3Q19Fused = 5;  // first fused variant
 const int kD3Q19TileCount = sizeof(kD3Q19Tiles) / sizeof(kD3Q19Tiles[0]);
 
 namespace {
@@ -604,9 +959,25 @@ void launch_fields_t(const CaseDev& c, const d3q19::Fields3& fl, int want_lmu, i
                        dim3(FX * FY * FZ), 0, s, c, fl, want_lmu, parity);
 }
 
+template <int S, int TX, int TY>
+void launch_slab(const CaseDev& c, int parity, int zs, hipStream_t s) {
+  const int ft = ((c.nx + TX - 1) / TX) * ((c.ny + TY - 1) / TY) * ((c.nz + zs - 1) / zs);
+  hipLaunchKernelGGL((d3q19::k3_slab<S, TX, TY>), dim3(8 * ((ft + 7) / 8)), dim3(TX * TY), 0,
+                     s, c, parity, zs);
+}
+
 template <int S>
 hipError_t pipeline(int variant, const CaseDev& c, int parity, const d3q19::Fields3& fl,
                     int want_lmu, bool collide, hipStream_t s) {
+  if (variant >= kD3Q19Fused && variant < kD3Q19TileCount) {
+    if (collide && !c.phiv) {
+      const TileShape& t = kD3Q19Tiles[variant];
+      if (t.tx == 32 && t.ty == 8) launch_slab<S, 32, 8>(c, parity, t.tz, s);
+      else launch_slab<S, 32, 16>(c, parity, t.tz, s);
+      return hipGetLastError();
+    }
+    variant = 1;
+  }
   const d3q19::RowGrid rg = d3q19::row_grid(c);
   if (rg.grid.y > 65535u) return hipErrorInvalidConfiguration;
   hipLaunchKernelGGL(d3q19::k3_pull<S>, rg.grid, rg.block, 0, s, c, parity, fl);

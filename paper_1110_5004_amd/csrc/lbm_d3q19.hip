@@ -916,12 +916,13 @@ k3_init(CaseDev c, int parity, const double* __restrict__ phi0, const double* __
 
 // ------------------------------------------------------------ launchers
 // Variants 0-4: the three-kernel step, by the tile of its fields kernel (the
-// pull and collision kernels are node-parallel, 256 threads).  Variants 5-8:
+// pull and collision kernels are node-parallel, 256 threads).  Variants 5-10:
 // the fused step, by its x-y tile and z chunk (tz planes).  All give the same
 // bits; the correction from data always takes the three-kernel step (tile 1).
 const TileShape kD3Q19Tiles[] = {{16, 8, 4, 512, 0},  {32, 4, 4, 512, 0},  {32, 8, 2, 512, 0},
                                  {16, 16, 2, 512, 0}, {8, 8, 8, 512, 0},   {32, 8, 16, 256, 0},
-                                 {32, 8, 32, 256, 0}, {32, 16, 16, 512, 0}, {32, 16, 32, 512, 0}};
+                                 {32, 8, 32, 256, 0}, {32, 16, 16, 512, 0}, {32, 16, 32, 512, 0},
+                                 {32, 8, 64, 256, 0}, {32, 16, 64, 512, 0}};
 constexpr int kD3Q19Fused = 5;  // first fused variant
 const int kD3Q19TileCount = sizeof(kD3Q19Tiles) / sizeof(kD3Q19Tiles[0]);
 

@@ -2,13 +2,17 @@
 //
 // The same model as the D2Q9 step (Eq. 1a, Eq. 4a, Eq. 8, the -F_a switch of
 // the paragraph after Eq. 12, isotropic central stencils), on 19 velocities.
-// A step is three kernels that pass fields through HBM:
+// A step is either the fused kernel
+//   k3_slab      one x-y tile marching up a z chunk, phi / mu / p rings in
+//                LDS, the whole step per plane (see its comment)
+// or three kernels that pass fields through HBM:
 //   k3_pull      pull f and gbar; phi (float-float) and the gbar moments
 //   k3_fields_t  on LDS tiles: mu = theta'(phi) - kappa lap phi, then grad
 //                phi, lap mu, u and p (with -F_a in the corrected model)
 //   k3_collide   grad p -> grad psi, BGK collision of f and gbar, store
-// Stencil neighbours come from the field planes through the periodic / mirror
-// mapping, so positions beyond a wall read their mirror node.
+// Both compute every node to the same bits.  Stencil neighbours go through
+// the periodic / mirror mapping, so positions beyond a wall read their mirror
+// node.
 #include "lbm_dev.h"
 #include "lbm_kernels.h"
 #include "lbm_lattice.h"

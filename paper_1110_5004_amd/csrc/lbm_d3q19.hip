@@ -662,6 +662,10 @@ __global__ void __launch_bounds__(TX * TY) k3_slab(CaseDev c, int parity, int zs
   // own node's pulled f_1..f_18 at planes z, z + 1, z + 2 and z + 3 (fn)
   float fa[Q], fb[Q], fc[Q], fn[Q];
   for (int z = za - 6; z < zb; ++z) {
+    // the own node's gbar for the collision at the end of the iteration: issued
+    // first, so the loads complete while phi, mu, u and p are formed
+    float gv[Q];
+    if (z >= za && own) pull_g<S>(c, src, Node3(c, gx, gy, z), gv);
     // P: phi at plane z + 3 over the tile + 3: first each thread's own node,
     // whose pulled f_1..f_18 it keeps for the collision of that plane three
     // iterations later, then the 3-wide ring around the tile
@@ -815,8 +819,6 @@ __global__ void __launch_bounds__(TX * TY) k3_slab(CaseDev c, int parity, int zs
     // C: grad p and the collision of the tile's nodes at plane z
     if (z >= za && own) {
       const Node3 nd(c, gx, gy, z);
-      float gv[Q];
-      pull_g<S>(c, src, nd, gv);
       const int uc = (lx + 1) + UX * (ly + 1);
       const int pm = slot3(zread(c, z - 1)) * T::NU, p0 = slot3(z) * T::NU,
                 pq = slot3(zread(c, z + 1)) * T::NU;

@@ -577,9 +577,12 @@ __global__ void __launch_bounds__(256) k3_collide(CaseDev c, int parity, Fields3
 //   p over the tile + 1, 3 planes
 // and iteration z stages phi(z + 3), forms mu(z + 2), pulls the gbar moments
 // and forms u and p at z + 1 (the tile's own nodes keep u, grad phi, mu and the
-// correction coefficient in registers), then collides plane z.  Populations
-// come from HBM once: the halo positions and the second read by the collision
-// are L2 hits, and no field plane goes through HBM.
+// correction coefficient in registers), then collides plane z.  No field plane
+// goes through HBM, and each population is fetched from it about once: a
+// thread keeps its own node's pulled f_1..f_18 in registers from the phi stage
+// to the collision three planes later, reads that node's gbar again at the top
+// of the next iteration while it is still in L2, and the halo positions mostly
+// hit L2.
 //
 // Positions beyond a wall: phi is staged from the mirror node (periodic image
 // on periodic axes); in the x-y plane mu, u and p at such a position are
@@ -588,8 +591,8 @@ __global__ void __launch_bounds__(256) k3_collide(CaseDev c, int parity, Fields3
 // mirror plane (a halfway wall mirrors the plane next to it).  Every quantity
 // is the same expression, in the same order, as in the three-kernel step, so
 // the two give the same bits.  The correction from data takes the
-// three-kernel step (it needs rho u_o over the tile + 1 of the previous
-// recovery).
+// three-kernel step: its rate needs the divergence of rho u_o, one more
+// stencil level, which would add a ring and a plane of lag.
 template <int TX, int TY>
 struct SlabLds {
   static constexpr int PX = TX + 6, PY = TY + 6, NP = PX * PY;  // phi plane
@@ -632,8 +635,9 @@ __device__ __forceinline__ float slab_mu(const CaseDev& c, const float* ph, cons
 template <int S, int TX, int TY>
 __global__ void __launch_bounds__(TX * TY) k3_slab(CaseDev c, int parity, int zs) {
   using T = SlabLds<TX, TY>;
-  constexpr int NT = TX * TY, PX = T::PX, MX = T::MX, UX = T::UX, UY = T::UY;
-  constexpr int NRING = T::NU - NT;  // positions of the tile + 1 outside the tile
+  constexpr int NT = TX * TY, PX = T::PX, PY = T::PY, MX = T::MX, UX = T::UX, UY = T::UY;
+  constexpr int NPRING = T::NP - NT;  // positions of the tile + 3 outside the tile
+  constexpr int NRING = T::NU - NT;   // positions of the tile + 1 outside the tile
   __shared__ T L;
   // XCD-aware tile order as in the fields kernel; x fastest, then y, then the
   // z chunk, so an XCD's consecutive tiles share their x-y halos
@@ -656,8 +660,6 @@ __global__ void __launch_bounds__(TX * TY) k3_slab(CaseDev c, int parity, int zs
   float* const mup = &L.mu[0][0];
   float* const pp = &L.p[0][0];
 
-  constexpr int PY = T::PY;
-  constexpr int NPRING = T::NP - NT;  // positions of the tile + 3 outside the tile
   NodeFields cur{}, nxt{};  // own node: plane z (collided now), plane z + 1
   // own node's pulled f_1..f_18 at planes z, z + 1, z + 2 and z + 3 (fn)
   float fa[Q], fb[Q], fc[Q], fn[Q];

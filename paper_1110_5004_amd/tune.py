@@ -24,7 +24,10 @@ def _key(sim):
     bucket = 2 ** int(round(math.log2(max(nodes, 1))))
     rf = max(int(q["remove_fa"]) for q in sim.params)
     st = sim.storage_name
-    return f"lat{p['lattice']}_{st}_rf{rf}_n{bucket}_c{len(sim.dims)}"
+    # the number of compiled variants: a library with another variant table
+    # does not reuse the winner measured on this one
+    nv = len(B.variants(p["lattice"]))
+    return f"lat{p['lattice']}_{st}_rf{rf}_n{bucket}_c{len(sim.dims)}_v{nv}"
 
 
 def load_cache(path=CACHE):

@@ -9,7 +9,8 @@
 //   k3_pull      pull f and gbar; phi (float-float) and the gbar moments
 //   k3_fields_t  on LDS tiles: mu = theta'(phi) - kappa lap phi, then grad
 //                phi, lap mu, u and p (with -F_a in the corrected model)
-//   k3_collide   grad p -> grad psi, BGK collision of f and gbar, store
+//   k3_collide   grad phi and mu again from the phi planes, grad p ->
+//                grad psi, BGK collision of f and gbar, store
 // Both compute every node to the same bits.  Stencil neighbours go through
 // the periodic / mirror mapping, so positions beyond a wall read their mirror
 // node.
@@ -122,7 +123,7 @@ inline RowGrid row_grid(const CaseDev& c) {
 struct Fields3 {
   float *phh, *phl, *m0, *m1x, *m1y, *m1z;  // pull
   float* mu;                                // mu
-  float *ux, *uy, *uz, *p, *lmu, *gx, *gy, *gz;  // fields
+  float *ux, *uy, *uz, *p, *lmu;                 // fields
   float* dd;  // correction from data: the rate D of -F_a = D u
 };
 
@@ -226,7 +227,7 @@ __device__ __forceinline__ constexpr int nofs(int i) {
 // the current state copy, in place of the Eq. 5 coefficient.
 template <int TX, int TY, int TZ, bool RF2>
 __global__ void __launch_bounds__(TX * TY * TZ)
-k3_fields_t(CaseDev c, Fields3 fl, int want_lmu, int parity) {
+k3_fields_t(CaseDev c, Fields3 fl, int dump, int parity) {
   using T = FieldTile<TX, TY, TZ, RF2>;
   constexpr int PX = T::PX, PY = T::PY, MX = T::MX, MY = T::MY;
   __shared__ T L;
@@ -357,7 +358,7 @@ k3_fields_t(CaseDev c, Fields3 fl, int want_lmu, int parity) {
   }
   const float mu = L.mu[mc];
   float lmu = 0.0f;
-  if (want_lmu || c.corr != 0.0f) {
+  if (dump || c.corr != 0.0f) {
     float la = 0.0f, le = 0.0f;
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
@@ -393,15 +394,14 @@ k3_fields_t(CaseDev c, Fields3 fl, int want_lmu, int parity) {
   const float ux = (3.0f * m1x + 0.5f * fsx) * iden;
   const float uy = (3.0f * m1y + 0.5f * fsy) * iden;
   const float uz = (3.0f * m1z + 0.5f * fsz) * iden;
-  fl.mu[idx] = mu;
+  // mu for the field dump only: the collision forms mu and grad phi again from
+  // the phi planes (phi_grad_mu), with these expressions in this order
+  if (dump) fl.mu[idx] = mu;
   fl.ux[idx] = ux;
   fl.uy[idx] = uy;
   fl.uz[idx] = uz;
   fl.p[idx] = m0 + (1.0f / 6.0f) * c.drho * (ux * g[0] + uy * g[1] + uz * g[2]);
   fl.lmu[idx] = lmu;
-  fl.gx[idx] = g[0];
-  fl.gy[idx] = g[1];
-  fl.gz[idx] = g[2];
 }
 
 // ---- 4: collision and store
@@ -535,6 +535,35 @@ __device__ __forceinline__ void pull_g(const CaseDev& c, const char* src, const 
   for (int i = 0; i < Q; ++i) gv[i] = P::g(c, src, pull3<S, true, N>(c, nd, i), WT(i));
 }
 
+// phi (float-float), grad phi and mu = theta'(phi) - kappa lap phi of a node
+// from the phi planes: the fields kernel's expressions, summed in its order
+// over the same neighbour values (mirror node across a wall, image across a
+// periodic seam), so the same bits as the values it formed in LDS.
+__device__ __forceinline__ void phi_grad_mu(const CaseDev& c, const Fields3& fl, const Node3& nd,
+                                            NodeFields& n) {
+  const float h0 = fl.phh[nd.idx], l0 = fl.phl[nd.idx];
+  float la = 0.0f, le = 0.0f;
+  float g[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+  for (int i = 1; i < Q; ++i) {
+    const unsigned j = nbr3(c, nd, i);
+    const float d = (fl.phh[j] - h0) + (fl.phl[j] - l0);
+    if (i <= 6) la += d;
+    else le += d;
+    const float w = i <= 6 ? (1.0f / 6.0f) : (1.0f / 12.0f);  // 3 w_i
+    if (EX(i)) g[0] += EX(i) > 0 ? w * d : -w * d;
+    if (EY(i)) g[1] += EY(i) > 0 ? w * d : -w * d;
+    if (EZ(i)) g[2] += EZ(i) > 0 ? w * d : -w * d;
+  }
+  const float lap = (1.0f / 3.0f) * la + (1.0f / 6.0f) * le;
+  n.phh = h0;
+  n.phl = l0;
+  n.mu = dtheta(c, h0, l0) - c.kappa * lap;
+  n.gx = g[0];
+  n.gy = g[1];
+  n.gz = g[2];
+}
+
 template <int S>
 __global__ void __launch_bounds__(256) k3_collide(CaseDev c, int parity, Fields3 fl) {
   const int x = blockIdx.y * blockDim.x + threadIdx.x;
@@ -549,17 +578,12 @@ __global__ void __launch_bounds__(256) k3_collide(CaseDev c, int parity, Fields3
   float gp[3];
   grad_f(c, fl.p, nd, gp);
   NodeFields n;
-  n.phh = fl.phh[idx];
-  n.phl = fl.phl[idx];
-  n.mu = fl.mu[idx];
+  phi_grad_mu(c, fl, nd, n);
   n.cc = c.phiv ? fl.dd[idx] : c.corr * fl.lmu[idx];
   n.p = fl.p[idx];
   n.ux = fl.ux[idx];
   n.uy = fl.uy[idx];
   n.uz = fl.uz[idx];
-  n.gx = fl.gx[idx];
-  n.gy = fl.gy[idx];
-  n.gz = fl.gz[idx];
   n.gpx = gp[0];
   n.gpy = gp[1];
   n.gpz = gp[2];
@@ -949,23 +973,20 @@ d3q19::Fields3 fields3(const Field3Ptrs& f) {
   fl.uz = f.plane[9];
   fl.p = f.plane[10];
   fl.lmu = f.plane[11];
-  fl.gx = f.plane[12];
-  fl.gy = f.plane[13];
-  fl.gz = f.plane[14];
-  fl.dd = f.plane[15];
+  fl.dd = f.plane[12];
   return fl;
 }
 
 template <int FX, int FY, int FZ>
-void launch_fields_t(const CaseDev& c, const d3q19::Fields3& fl, int want_lmu, int parity,
+void launch_fields_t(const CaseDev& c, const d3q19::Fields3& fl, int dump, int parity,
                      hipStream_t s) {
   const int ft = ((c.nx + FX - 1) / FX) * ((c.ny + FY - 1) / FY) * ((c.nz + FZ - 1) / FZ);
   if (c.phiv)
     hipLaunchKernelGGL((d3q19::k3_fields_t<FX, FY, FZ, true>), dim3(8 * ((ft + 7) / 8)),
-                       dim3(FX * FY * FZ), 0, s, c, fl, want_lmu, parity);
+                       dim3(FX * FY * FZ), 0, s, c, fl, dump, parity);
   else
     hipLaunchKernelGGL((d3q19::k3_fields_t<FX, FY, FZ, false>), dim3(8 * ((ft + 7) / 8)),
-                       dim3(FX * FY * FZ), 0, s, c, fl, want_lmu, parity);
+                       dim3(FX * FY * FZ), 0, s, c, fl, dump, parity);
 }
 
 template <int S, int TX, int TY>
@@ -977,7 +998,7 @@ void launch_slab(const CaseDev& c, int parity, int zs, hipStream_t s) {
 
 template <int S>
 hipError_t pipeline(int variant, const CaseDev& c, int parity, const d3q19::Fields3& fl,
-                    int want_lmu, bool collide, hipStream_t s) {
+                    int dump, bool collide, hipStream_t s) {
   if (variant >= kD3Q19Fused && variant < kD3Q19TileCount) {
     if (collide && !c.phiv) {
       const TileShape& t = kD3Q19Tiles[variant];
@@ -991,11 +1012,11 @@ hipError_t pipeline(int variant, const CaseDev& c, int parity, const d3q19::Fiel
   if (rg.grid.y > 65535u) return hipErrorInvalidConfiguration;
   hipLaunchKernelGGL(d3q19::k3_pull<S>, rg.grid, rg.block, 0, s, c, parity, fl);
   switch (variant) {
-    case 0: launch_fields_t<16, 8, 4>(c, fl, want_lmu, parity, s); break;
-    case 1: launch_fields_t<32, 4, 4>(c, fl, want_lmu, parity, s); break;
-    case 2: launch_fields_t<32, 8, 2>(c, fl, want_lmu, parity, s); break;
-    case 3: launch_fields_t<16, 16, 2>(c, fl, want_lmu, parity, s); break;
-    case 4: launch_fields_t<8, 8, 8>(c, fl, want_lmu, parity, s); break;
+    case 0: launch_fields_t<16, 8, 4>(c, fl, dump, parity, s); break;
+    case 1: launch_fields_t<32, 4, 4>(c, fl, dump, parity, s); break;
+    case 2: launch_fields_t<32, 8, 2>(c, fl, dump, parity, s); break;
+    case 3: launch_fields_t<16, 16, 2>(c, fl, dump, parity, s); break;
+    case 4: launch_fields_t<8, 8, 8>(c, fl, dump, parity, s); break;
     default: return hipErrorInvalidValue;
   }
   if (collide) hipLaunchKernelGGL(d3q19::k3_collide<S>, rg.grid, rg.block, 0, s, c, parity, fl);

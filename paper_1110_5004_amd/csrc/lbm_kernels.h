@@ -46,9 +46,9 @@ hipError_t d2q9_init(const CaseDev& c, int storage, int parity, const double* ph
                      const double* u0, const double* p0, hipStream_t stream);
 
 // D3Q19: per case and step either the fused kernel (no field planes) or three
-// kernels passing 16 field planes (phi hi/lo, gbar moments, mu, u, p, lap mu,
-// grad phi, and the rate D of the correction from data).
-constexpr int kField3Planes = 16;
+// kernels passing 13 field planes (phi hi/lo, gbar moments, mu (field dump
+// only), u, p, lap mu, and the rate D of the correction from data).
+constexpr int kField3Planes = 13;
 struct Field3Ptrs {
   float* plane[kField3Planes];
 };

@@ -154,8 +154,9 @@ int lbm_init(const lbm_case_params* cases, int32_t ncases, const double* const* 
              size_t arena_bytes, void* hip_stream, int32_t check_every,
              lbm_handle** out);
 
-/* Advance every case by nsteps time steps (fields, collision, streaming in
- * one fused kernel per step; repeated steps replay a captured HIP graph).
+/* Advance every case by nsteps time steps (fields, collision and streaming in
+ * one fused kernel per step, or for D3Q19 in the three-kernel form when the
+ * launch variant selects it; repeated steps replay a captured HIP graph).
  * Asynchronous unless check_every triggers a check. */
 int lbm_step(lbm_handle* h, int64_t nsteps);
 

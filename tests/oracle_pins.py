@@ -221,6 +221,77 @@ def check_mirror_ghosts(lib):
     assert np.allclose(l_w.reshape(ny, nx), l_p.reshape(ny, 2 * nx)[:, :nx], atol=1e-14)
 
 
+def check_stencils_d3q19(lib):
+    """The D3Q19 stencils (18 neighbours, weights 1/18 and 1/36):
+    exact on a quadratic in x, y, z plus x^3 away from the seams (the
+    isotropic first derivative of x^3 is 3x^2 + 1, as in 2-D, since
+    3 sum w e_x^3 = 1 on this lattice too; the Laplacian of x^3 is exact),
+    second-order convergence on sin kx sin 2ky sin kz, an isotropic leading
+    error on a Gaussian (same error along an axis, a face diagonal in the xy
+    plane and one in the yz plane), and wall ghosts equal to a doubled periodic
+    grid holding the field and its reflection in z."""
+    def grid(nx, ny, nz):
+        z, y, x = np.meshgrid(np.arange(nz, dtype=float), np.arange(ny, dtype=float),
+                              np.arange(nx, dtype=float), indexing="ij")
+        return x, y, z
+
+    n = 12
+    case = _case(n, n, nz=n, lattice=W.D3Q19)
+    x, y, z = grid(n, n, n)
+    a, b, c, d, e, f, gx_, gy_, gz_ = 0.3, -0.7, 0.45, 0.2, 0.55, -0.35, 1.1, -0.2, 0.6
+    fld = (a * x**2 + b * x * y + c * y**2 + d * z**2 + e * x * z + f * y * z
+           + gx_ * x + gy_ * y + gz_ * z + 0.01 * x**3)
+    g, lap = O.grad_lap(case, fld.ravel(), lib)
+    g = g.reshape(3, n, n, n)
+    lap = lap.reshape(n, n, n)
+    inner = (slice(2, n - 2),) * 3
+    want = [2 * a * x + b * y + e * z + gx_ + 0.03 * x**2 + 0.01,
+            b * x + 2 * c * y + f * z + gy_,
+            2 * d * z + e * x + f * y + gz_]
+    for k in range(3):
+        assert np.allclose(g[k][inner], want[k][inner], atol=1e-10), k
+    assert np.allclose(lap[inner], (2 * a + 2 * c + 2 * d + 0.06 * x)[inner], atol=1e-10)
+
+    errs = []
+    for n in (16, 32, 64):
+        case = _case(n, n, nz=n, lattice=W.D3Q19)
+        x, y, z = grid(n, n, n)
+        k = 2 * math.pi / n
+        fld = np.sin(k * x) * np.sin(2 * k * y) * np.sin(k * z)
+        g, lap = O.grad_lap(case, fld.ravel(), lib)
+        ex = k * np.cos(k * x) * np.sin(2 * k * y) * np.sin(k * z)
+        ey = 2 * k * np.sin(k * x) * np.cos(2 * k * y) * np.sin(k * z)
+        ez = k * np.sin(k * x) * np.sin(2 * k * y) * np.cos(k * z)
+        el = -6 * k * k * fld
+        errs.append((np.abs(g[0] - ex.ravel()).max() / k, np.abs(g[1] - ey.ravel()).max() / k,
+                     np.abs(g[2] - ez.ravel()).max() / k, np.abs(lap - el.ravel()).max() / k**2))
+    errs = np.array(errs)
+    slopes = np.log2(errs[:-1] / errs[1:])
+    assert (slopes > 1.9).all() and (slopes < 2.1).all(), slopes
+
+    n = 32
+    case = _case(n, n, nz=n, lattice=W.D3Q19)
+    x, y, z = grid(n, n, n)
+    s2 = 16.0
+    r2 = (x - 16) ** 2 + (y - 16) ** 2 + (z - 16) ** 2
+    fld = np.exp(-r2 / s2)
+    _, lap = O.grad_lap(case, fld.ravel(), lib)
+    err = lap.reshape(n, n, n) - (4 * r2 / s2**2 - 6 / s2) * fld
+    e_axis, e_xy, e_yz = err[16, 16, 21], err[16, 20, 19], err[19, 20, 16]
+    assert abs(e_axis - e_xy) < 0.1 * abs(e_axis), (e_axis, e_xy)
+    assert abs(e_axis - e_yz) < 0.1 * abs(e_axis), (e_axis, e_yz)
+
+    rng = np.random.default_rng(6)
+    nx, ny, nz = 6, 5, 7
+    fld = rng.standard_normal((nz, ny, nx))
+    g_w, l_w = O.grad_lap(_case(nx, ny, (0, 0, 1), nz=nz, lattice=W.D3Q19), fld.ravel(), lib)
+    big = np.concatenate([fld, fld[::-1]], axis=0)
+    g_p, l_p = O.grad_lap(_case(nx, ny, nz=2 * nz, lattice=W.D3Q19), big.ravel(), lib)
+    assert np.allclose(g_w.reshape(3, nz, ny, nx), g_p.reshape(3, 2 * nz, ny, nx)[:, :nz],
+                       atol=1e-14)
+    assert np.allclose(l_w.reshape(nz, ny, nx), l_p.reshape(2 * nz, ny, nx)[:nz], atol=1e-14)
+
+
 # ------------------------------------------------------- P7/P8 thermodynamics
 def _uniform_mu(lib, phi, beta_sigma=0.01, width=4.0):
     n = 4
@@ -873,7 +944,8 @@ def check_symmetric_well(lib):
 
 ALL_CHECKS = [check_lattice, check_feq_moments, check_geq_moments, check_source_moments,
               check_recover, check_stencil_polynomials, check_stencil_convergence,
-              check_stencil_isotropy, check_mirror_ghosts, check_chemical_potential,
+              check_stencil_isotropy, check_mirror_ghosts, check_stencils_d3q19,
+              check_chemical_potential,
               check_beta_kappa, check_stream_permutation, check_fixed_point,
               check_uniform_flow, check_conservation, check_uniform_force,
               check_shear_wave, check_ch_diffusion, check_switch_noop, check_fa_field,

@@ -93,6 +93,10 @@ MUTANTS = [
      "for (int k = 0; k < dim; ++k) s->rhou[k * n + idx] = s->rho[idx] * s->u[k * n + idx];"),
     ("data_rate_sign", "if (p->remove_fa == 2) c = s->dmass[idx];",
      "if (p->remove_fa == 2) c = -s->dmass[idx];"),
+    ("d3q19_edge_weight", "L->w[i] = (i == 0) ? 1.0 / 3.0 : (i <= 6 ? 1.0 / 18.0 : 1.0 / 36.0);",
+     "L->w[i] = (i == 0) ? 1.0 / 3.0 : (i <= 6 ? 1.0 / 18.0 : 1.0 / 18.0);"),
+    ("d3q19_edge_vector", "{-1, 1, 0}, {1, 0, 1},   {-1, 0, -1}, {1, 0, -1}, {-1, 0, 1},",
+     "{-1, 1, 0}, {1, 0, 1},   {-1, 0, -1}, {1, 0, 1}, {-1, 0, -1},"),
 ]
 
 FAST_CHECKS = [c for c in P.ALL_CHECKS]

@@ -230,7 +230,8 @@ int lbm_set_step(lbm_handle* h, int64_t step);
 
 /* Launch shape.  variant indexes the compiled tile shapes (lbm_variant_info);
  * grid_blocks = 0 launches one workgroup per tile, otherwise that many
- * workgroups loop over the tiles.  graph_steps = 0 disables graph capture,
+ * workgroups loop over the tiles (D2Q9; the D3Q19 kernels always launch one
+ * workgroup per tile and ignore it).  graph_steps = 0 disables graph capture,
  * otherwise lbm_step replays a graph of that many (even) steps. */
 int lbm_set_launch(lbm_handle* h, int32_t variant, int32_t grid_blocks, int32_t graph_steps);
 int lbm_get_launch(const lbm_handle* h, int32_t* variant, int32_t* grid_blocks,

@@ -240,9 +240,8 @@ int lbm_get_launch(const lbm_handle* h, int32_t* variant, int32_t* grid_blocks,
  * axis) and workgroup size of one.  D3Q19: variants whose tz is below 16 are
  * the three-kernel step, named by the tile of its fields kernel; those with tz
  * of 16 or more are the fused step, one tx x ty tile of the x-y plane marching
- * up a chunk of tz planes (the correction from data, remove_fa = 2, always
- * takes the three-kernel step).  Every variant of a lattice computes the same
- * bits. */
+ * up a chunk of tz planes.  Every variant of a lattice computes the same bits,
+ * in every model and storage layout. */
 int lbm_variant_count(int32_t lattice, int32_t* count);
 int lbm_variant_info(int32_t lattice, int32_t variant, int32_t* tx, int32_t* ty, int32_t* tz,
                      int32_t* threads);

@@ -614,18 +614,27 @@ __global__ void __launch_bounds__(256) k3_collide(CaseDev c, int parity, Fields3
 // along z the planes beyond a wall are not formed and their reads go to the
 // mirror plane (a halfway wall mirrors the plane next to it).  Every quantity
 // is the same expression, in the same order, as in the three-kernel step, so
-// the two give the same bits.  The correction from data takes the
-// three-kernel step: its rate needs the divergence of rho u_o, one more
-// stencil level, which would add a ring and a plane of lag.
-template <int TX, int TY>
+// the two give the same bits.
+//
+// RF2 (correction from data): the mu stage also forms rho u_o, the
+// uncorrected recovery, over the tile + 2 (a fourth ring, 3 planes), and the
+// u and p stage takes as the coefficient of -F_a the rate
+// D = drho (phi - phi^(n-1)) + div(rho u_o) in place of the Eq. 5 one, with
+// phi^(n-1) from the plane of the source copy; the collision writes phi to the
+// plane of the destination copy.  The divergence replaces lap mu, so the
+// pipeline keeps its depth.
+template <int TX, int TY, bool RF2>
 struct SlabLds {
   static constexpr int PX = TX + 6, PY = TY + 6, NP = PX * PY;  // phi plane
   static constexpr int MX = TX + 4, MY = TY + 4, NM = MX * MY;  // mu plane
   static constexpr int UX = TX + 2, UY = TY + 2, NU = UX * UY;  // p plane
+  static constexpr int NQ = RF2 ? NM : 1;
   float ph[4][NP];
   float pl[4][NP];
   float mu[3][NM];
   float p[3][NU];
+  float q[3][3][NQ];  // RF2: rho u_o, plane slot x component
+  float m[2][4][NQ];  // RF2: the gbar moments m0, m1 behind it, for the u, p stage
 };
 
 // Ring slot of plane k (k >= -6).
@@ -656,9 +665,9 @@ __device__ __forceinline__ float slab_mu(const CaseDev& c, const float* ph, cons
   return dtheta(c, h0, l0) - c.kappa * lap;
 }
 
-template <int S, int TX, int TY>
+template <int S, int TX, int TY, bool RF2>
 __global__ void __launch_bounds__(TX * TY) k3_slab(CaseDev c, int parity, int zs) {
-  using T = SlabLds<TX, TY>;
+  using T = SlabLds<TX, TY, RF2>;
   constexpr int NT = TX * TY, PX = T::PX, PY = T::PY, MX = T::MX, UX = T::UX, UY = T::UY;
   constexpr int NPRING = T::NP - NT;  // positions of the tile + 3 outside the tile
   constexpr int NRING = T::NU - NT;   // positions of the tile + 1 outside the tile
@@ -740,13 +749,49 @@ __global__ void __launch_bounds__(TX * TY) k3_slab(CaseDev c, int parity, int zs
       if (k >= za - 2 && !(c.wall_z && (k < 0 || k >= c.nz))) {
         const int bm = slot4(k - 1) * T::NP, b0 = slot4(k) * T::NP, bp = slot4(k + 1) * T::NP;
         const int b = slot3(k) * T::NM;
+        const int qz = fold3(k, c.nz, c.wall_z);
         for (int pos = tid; pos < T::NM; pos += NT) {
           int mx = pos % MX, my = pos / MX;
           if (!inner) {
             mx = mirror_local(mx, x0 - 2, c.nx, c.wall_x, MX);
             my = mirror_local(my, y0 - 2, c.ny, c.wall_y, T::MY);
           }
-          mup[b + pos] = slab_mu<PX>(c, php, plp, bm, b0, bp, (mx + 1) + PX * (my + 1));
+          const int pc = (mx + 1) + PX * (my + 1);
+          const float mu = slab_mu<PX>(c, php, plp, bm, b0, bp, pc);
+          mup[b + pos] = mu;
+          if constexpr (RF2) {
+            // rho u_o at the same position: the mirror node's moments and the
+            // stencil around the mirror position
+            int qx = x0 - 2 + pos % MX, qy = y0 - 2 + pos / MX;
+            if (!inner) {
+              qx = fold3(qx, c.nx, c.wall_x);
+              qy = fold3(qy, c.ny, c.wall_y);
+            }
+            float m0, m1x, m1y, m1z;
+            pull_moments<S>(c, src, Node3(c, qx, qy, qz), m0, m1x, m1y, m1z);
+            const float h0 = php[b0 + pc], l0 = plp[b0 + pc];
+            float g[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int i = 1; i < Q; ++i) {
+              const int j = (EZ(i) < 0 ? bm : (EZ(i) > 0 ? bp : b0)) + pc + EX(i) + PX * EY(i);
+              const float d = (php[j] - h0) + (plp[j] - l0);
+              const float w = i <= 6 ? (1.0f / 6.0f) : (1.0f / 12.0f);  // 3 w_i
+              if (EX(i)) g[0] += EX(i) > 0 ? w * d : -w * d;
+              if (EY(i)) g[1] += EY(i) > 0 ? w * d : -w * d;
+              if (EZ(i)) g[2] += EZ(i) > 0 ? w * d : -w * d;
+            }
+            const float rho = c.rho0 + (h0 + l0) * c.drho;
+            const float iden = __builtin_amdgcn_rcpf(rho);
+            const float fsz = mu * g[2] - (rho - c.rho_ref) * c.gravity;
+            const int sq = slot3(k), sm = (k + 8) & 1;
+            L.m[sm][0][pos] = m0;
+            L.m[sm][1][pos] = m1x;
+            L.m[sm][2][pos] = m1y;
+            L.m[sm][3][pos] = m1z;
+            L.q[sq][0][pos] = rho * ((3.0f * m1x + 0.5f * (mu * g[0])) * iden);
+            L.q[sq][1][pos] = rho * ((3.0f * m1y + 0.5f * (mu * g[1])) * iden);
+            L.q[sq][2][pos] = rho * ((3.0f * m1z + 0.5f * fsz) * iden);
+          }
         }
       }
     }
@@ -786,7 +831,17 @@ __global__ void __launch_bounds__(TX * TY) k3_slab(CaseDev c, int parity, int zs
             qy = fold3(qy, c.ny, c.wall_y);
           }
           float m0, m1x, m1y, m1z;
-          pull_moments<S>(c, src, Node3(c, qx, qy, qz), m0, m1x, m1y, m1z);
+          const Node3 nq(c, qx, qy, qz);
+          if constexpr (RF2) {
+            // the mu stage of the previous iteration pulled them at this node
+            const int sm = (k + 8) & 1, jm = (ux + 1) + MX * (uy + 1);
+            m0 = L.m[sm][0][jm];
+            m1x = L.m[sm][1][jm];
+            m1y = L.m[sm][2][jm];
+            m1z = L.m[sm][3][jm];
+          } else {
+            pull_moments<S>(c, src, nq, m0, m1x, m1y, m1z);
+          }
           const int pc = (mx + 2) + PX * (my + 2);
           const int mc = (mx + 1) + MX * (my + 1);
           const float h0 = php[b0 + pc], l0 = plp[b0 + pc];
@@ -817,7 +872,23 @@ __global__ void __launch_bounds__(TX * TY) k3_slab(CaseDev c, int parity, int zs
           const float rho = c.rho0 + ph * c.drho;
           const float fsx = mu * g[0], fsy = mu * g[1];
           const float fsz = mu * g[2] - (rho - c.rho_ref) * c.gravity;
-          const float cc = c.corr * lmu;
+          float cc = c.corr * lmu;
+          if constexpr (RF2) {
+            const int qm = slot3(zread(c, k - 1)), q0 = slot3(k), qp = slot3(zread(c, k + 1));
+            float dv = 0.0f;
+#pragma unroll
+            for (int i = 1; i < Q; ++i) {
+              const int sl = EZ(i) < 0 ? qm : (EZ(i) > 0 ? qp : q0);
+              const int j = mc + EX(i) + MX * EY(i);
+              const float w = i <= 6 ? (1.0f / 6.0f) : (1.0f / 12.0f);  // 3 w_i
+              float e = 0.0f;
+              if (EX(i)) e += EX(i) > 0 ? L.q[sl][0][j] : -L.q[sl][0][j];
+              if (EY(i)) e += EY(i) > 0 ? L.q[sl][1][j] : -L.q[sl][1][j];
+              if (EZ(i)) e += EZ(i) > 0 ? L.q[sl][2][j] : -L.q[sl][2][j];
+              dv += w * e;
+            }
+            cc = (ph - gload<float>(src, c.phiv + 4u * nq.idx)) * c.drho + dv;
+          }
           const float iden = __builtin_amdgcn_rcpf(rho - 0.5f * cc);
           const float vx = (3.0f * m1x + 0.5f * fsx) * iden;
           const float vy = (3.0f * m1y + 0.5f * fsy) * iden;
@@ -862,6 +933,8 @@ __global__ void __launch_bounds__(TX * TY) k3_slab(CaseDev c, int parity, int zs
       cur.gpy = ay;
       cur.gpz = az;
       collide_node<S>(c, op, nd.idx, fa, gv, cur);
+      // correction from data: the copy carries this step's phi
+      if constexpr (RF2) gstore<float>(op.base, c.phiv + 4u * nd.idx, cur.phh + cur.phl);
     }
     cur = nxt;
 #pragma unroll
@@ -950,7 +1023,7 @@ k3_init(CaseDev c, int parity, const double* __restrict__ phi0, const double* __
 // Variants 0-4: the three-kernel step, by the tile of its fields kernel (the
 // pull and collision kernels are node-parallel, 256 threads).  Variants 5-10:
 // the fused step, by its x-y tile and z chunk (tz planes).  All give the same
-// bits; the correction from data always takes the three-kernel step (tile 1).
+// bits, in every model and storage layout.
 const TileShape kD3Q19Tiles[] = {{16, 8, 4, 512, 0},  {32, 4, 4, 512, 0},  {32, 8, 2, 512, 0},
                                  {16, 16, 2, 512, 0}, {8, 8, 8, 512, 0},   {32, 8, 16, 256, 0},
                                  {32, 8, 32, 256, 0}, {32, 16, 16, 512, 0}, {32, 16, 32, 512, 0},
@@ -992,15 +1065,19 @@ void launch_fields_t(const CaseDev& c, const d3q19::Fields3& fl, int dump, int p
 template <int S, int TX, int TY>
 void launch_slab(const CaseDev& c, int parity, int zs, hipStream_t s) {
   const int ft = ((c.nx + TX - 1) / TX) * ((c.ny + TY - 1) / TY) * ((c.nz + zs - 1) / zs);
-  hipLaunchKernelGGL((d3q19::k3_slab<S, TX, TY>), dim3(8 * ((ft + 7) / 8)), dim3(TX * TY), 0,
-                     s, c, parity, zs);
+  if (c.phiv)
+    hipLaunchKernelGGL((d3q19::k3_slab<S, TX, TY, true>), dim3(8 * ((ft + 7) / 8)),
+                       dim3(TX * TY), 0, s, c, parity, zs);
+  else
+    hipLaunchKernelGGL((d3q19::k3_slab<S, TX, TY, false>), dim3(8 * ((ft + 7) / 8)),
+                       dim3(TX * TY), 0, s, c, parity, zs);
 }
 
 template <int S>
 hipError_t pipeline(int variant, const CaseDev& c, int parity, const d3q19::Fields3& fl,
                     int dump, bool collide, hipStream_t s) {
   if (variant >= kD3Q19Fused && variant < kD3Q19TileCount) {
-    if (collide && !c.phiv) {
+    if (collide) {
       const TileShape& t = kD3Q19Tiles[variant];
       if (t.tx == 32 && t.ty == 8) launch_slab<S, 32, 8>(c, parity, t.tz, s);
       else launch_slab<S, 32, 16>(c, parity, t.tz, s);

@@ -147,12 +147,14 @@ def _fused_variants(hip):
 @pytest.mark.parametrize("dims,wall", [((70, 40, 70), (0, 0, 1)), ((66, 36, 40), (1, 1, 1)),
                                        ((40, 20, 36), (0, 0, 0))])
 @pytest.mark.parametrize("storage,rf,well", [("fp32", 1, 0), ("fp16", 1, 0), ("bf16", 1, 0),
-                                             ("fp32", 0, 0), ("fp32", 1, 1)])
+                                             ("fp32", 0, 0), ("fp32", 1, 1), ("fp32", 2, 0),
+                                             ("fp16", 2, 0)])
 def test_fused_step_bitwise(hip, dims, wall, storage, rf, well):
     """The fused step (one x-y tile marching up a z chunk) against the
     three-kernel step: several x and y tiles, several z chunks, ragged edges,
-    walls and periodic seams on every axis; both models, the three storage
-    layouts and the symmetric well; 40 steps to the same bits."""
+    walls and periodic seams on every axis; the three models (F_a kept, removed
+    by Eq. 5, removed by the rate from the data), the three storage layouts and
+    the symmetric well; 40 steps to the same bits."""
     nx, ny, nz = dims
     prm = W.base_params(W.D3Q19, nx, ny, nz, wall, sigma=0.01, gravity=2e-5, remove_fa=rf,
                         tau_g=0.7, mu_ratio=4.0, well=well, phi_star=0.8)

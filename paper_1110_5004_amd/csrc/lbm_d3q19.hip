@@ -616,9 +616,11 @@ __global__ void __launch_bounds__(256) k3_collide(CaseDev c, int parity, Fields3
 // is the same expression, in the same order, as in the three-kernel step, so
 // the two give the same bits.
 //
-// RF2 (correction from data): the mu stage also forms rho u_o, the
-// uncorrected recovery, over the tile + 2 (a fourth ring, 3 planes), and the
-// u and p stage takes as the coefficient of -F_a the rate
+// RF2 (correction from data): the mu stage also pulls the gbar moments and
+// forms rho u_o, the uncorrected recovery, over the tile + 2 (a ring of 3
+// planes; the moments go to a ring of 2, which the u and p stage of the next
+// plane reads instead of pulling again), and the u and p stage takes as the
+// coefficient of -F_a the rate
 // D = drho (phi - phi^(n-1)) + div(rho u_o) in place of the Eq. 5 one, with
 // phi^(n-1) from the plane of the source copy; the collision writes phi to the
 // plane of the destination copy.  The divergence replaces lap mu, so the

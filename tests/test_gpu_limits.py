@@ -8,6 +8,9 @@ small grid: a step reads a node's neighbourhood within 4 nodes, so after k
 steps nothing beyond 4k nodes of the droplet has changed, and every node is
 computed by the same arithmetic from the same inputs.
 
+The same for D3Q19 (256 x 256 x 425 nodes at 154 B; 256 x 256 x 414 at 158
+B with the phi plane), for the three-kernel and the fused step.
+
 Smallest: 4 x 4 (and 5 x 4, 4 x 4 x 4) grids, where every tile shape is larger
 than the grid and most of each tile lies outside it, against the oracle."""
 import numpy as np
@@ -113,3 +116,63 @@ def test_smallest_grids(hip, dims, wall, rf):
         else:
             assert np.array_equal(sim.get_state(), first), f"variant {v} differs"
         sim.close()
+
+
+def _largest_3d(hip, rf, variant):
+    import torch
+    # 154 B per node, 158 with the phi plane of the correction from data
+    nz = 425 if rf != 2 else 414
+    big = (256, 256, nz)
+    steps = 8
+    # exactly representable fractions: both grids start from the same bits;
+    # far along z, so the window holds the highest node indices
+    cb = (128.25, 128.5, nz - 70 + 0.25)
+    n_s = 128
+    cs = (64.25, 64.5, 64.25)
+    prm = W.base_params(W.D3Q19, *big, (0, 0, 0), sigma=0.01, remove_fa=rf)
+    phi, u, p = W.droplet_fields(prm, cb, 10.0, impact_u=0.03)
+    sim = hip.Simulation([W.Case(prm, phi, u, p)])
+    del phi, u, p
+    per_copy = sim.state_bytes()
+    print(f"largest d3q19 rf={rf} variant {variant}: {big}, {per_copy} B per state copy")
+    assert 0.98 * 2**32 < per_copy < 2**32
+    sim.set_launch(variant, 0, 16)
+    sim.step(steps)
+    d = sim.diagnostics()
+    m = sim.moments_device()
+    x0, y0, z0 = (int(cb[k]) - n_s // 2 for k in range(3))
+    assert z0 + n_s <= nz
+    win = (slice(z0, z0 + n_s), slice(y0, y0 + n_s), slice(x0, x0 + n_s))
+    phi_b = m["phi"].view(nz, 256, 256)[win].cpu().numpy()
+    u_b = m["u"].view(3, nz, 256, 256)[(slice(None),) + win].cpu().numpy()
+    p_b = m["p"].view(nz, 256, 256)[win].cpu().numpy()
+    del m
+    sim.close()
+    torch.cuda.empty_cache()
+    prm_s = W.base_params(W.D3Q19, n_s, n_s, n_s, (0, 0, 0), sigma=0.01, remove_fa=rf)
+    ref = hip.Simulation([W.Case(prm_s, *W.droplet_fields(prm_s, cs, 10.0, impact_u=0.03))])
+    ref.set_launch(variant, 0, 16)
+    ref.step(steps)
+    r = ref.moments()
+    ref.close()
+    assert d["nonfinite"] == 0 and d["mass_drift_rel"] <= 1e-6
+    # a step reads within 4 nodes, so after k steps a node within 63 - 4k of
+    # the centre depends only on initial values within 63 of it, which the two
+    # grids share (the small grid wraps at 64); farther out the droplet's FP32
+    # tails (~1e-32) meet the small grid's periodic image
+    h = 63 - 4 * steps
+    core = (slice(n_s // 2 - h, n_s // 2 + h + 1),) * 3
+    assert np.array_equal(phi_b[core], r["phi"].reshape(n_s, n_s, n_s)[core])
+    assert np.array_equal(u_b[(slice(None),) + core],
+                          r["u"].reshape(3, n_s, n_s, n_s)[(slice(None),) + core])
+    assert np.array_equal(p_b[core], r["p"].reshape(n_s, n_s, n_s)[core])
+
+
+@pytest.mark.parametrize("rf,variant", [(1, 0), (1, 10), (2, 1), (2, 9)])
+def test_largest_copy_matches_small_grid_d3q19(hip, rf, variant):
+    """D3Q19 state copies just under 4 GiB (256 x 256 x 425 nodes at 154 B;
+    256 x 256 x 414 at 158 B with the phi plane), the three-kernel and the
+    fused step, droplet far along z, 8 steps: the 63^3 core of the window
+    around it (all nodes whose 8-step dependency cone the two grids share)
+    equals a 128^3 grid's run bit for bit."""
+    _largest_3d(hip, rf, variant)

@@ -107,3 +107,12 @@ def test_copy_over_4gib_rejected(L):
         c = B.make_case(_params(nx=8192, **kw))
         assert L.lbm_required_bytes(C.byref(c), 1, C.byref(nbytes)) == B.ERR_ARG
         assert "4 GiB" in L.lbm_last_error().decode()
+
+
+def test_empty_case_list_rejected(L):
+    """No cases, or no case array, is an argument error, not an empty handle."""
+    c = B.make_case(_params())
+    nbytes = C.c_size_t()
+    assert L.lbm_required_bytes(C.byref(c), 0, C.byref(nbytes)) == B.ERR_ARG
+    assert L.lbm_required_bytes(None, 1, C.byref(nbytes)) == B.ERR_ARG
+    assert L.lbm_last_error()

@@ -222,6 +222,30 @@ def test_checkpoint_resume_bitwise(torch, hip):
     assert np.array_equal(a.get_state(), c.get_state())
 
 
+@pytest.mark.parametrize("lattice", ["d2q9", "d3q19"])
+def test_zero_and_negative_steps(torch, hip, lattice):
+    """lbm_step(0) leaves the state and the time level untouched, for the
+    graph and the eager path; a negative count is an argument error."""
+    if lattice == "d2q9":
+        case = W.stationary_droplet(seed=2, n=64, radius=12.0, remove_fa=1)
+    else:
+        prm = W.base_params(W.D3Q19, 20, 18, 16, (0, 0, 1), sigma=0.01, remove_fa=1)
+        case = W.Case(prm, *W.droplet_fields(prm, (9.0, 9.0, 8.0), 5.0, impact_u=0.02))
+    for graph in (16, 0):
+        sim = hip.Simulation([case])
+        sim.set_launch(0, 0, graph)
+        sim.step(3)
+        st = sim.get_state()
+        sim.step(0)
+        assert sim.time == 3
+        assert np.array_equal(sim.get_state(), st)
+        with pytest.raises(hip.LbmError) as ei:
+            sim.step(-1)
+        assert ei.value.code == hip.binding.ERR_ARG
+        assert sim.time == 3
+        sim.close()
+
+
 def test_nonfinite_detected(torch, hip):
     case = W.stationary_droplet(seed=1, n=64, radius=12.0)
     phi = case.phi0.copy()

@@ -246,6 +246,32 @@ def test_zero_and_negative_steps(torch, hip, lattice):
         sim.close()
 
 
+@pytest.mark.parametrize("lattice,variant", [("d2q9", None), ("d3q19", 1), ("d3q19", 10)])
+@pytest.mark.parametrize("degenerate", [dict(theta_m=0.0), dict(rho_l=0.4, rho_g=0.4)])
+def test_switch_noop_bitwise(torch, hip, lattice, variant, degenerate):
+    """With theta_M = 0 or equal densities the Eq. 5 coefficient of F_a
+    vanishes, so removing F_a changes nothing: the original and the corrected
+    model give the same bits (D2Q9, and both D3Q19 step forms)."""
+    states = []
+    for rf in (0, 1):
+        if lattice == "d2q9":
+            prm = W.base_params(W.D2Q9, 48, 40, 1, (0, 1, 0), sigma=0.01, gravity=1e-5,
+                                remove_fa=rf, **degenerate)
+            centre = (20.3, 18.6)
+        else:
+            prm = W.base_params(W.D3Q19, 20, 18, 16, (0, 0, 1), sigma=0.01, gravity=1e-5,
+                                remove_fa=rf, **degenerate)
+            centre = (9.3, 8.6, 8.2)
+        case = W.Case(prm, *W.droplet_fields(prm, centre, 6.0, impact_u=0.02))
+        sim = hip.Simulation([case])
+        if variant is not None:
+            sim.set_launch(variant, 0, 16)
+        sim.step(60)
+        states.append(sim.get_state())
+        sim.close()
+    assert np.array_equal(states[0], states[1])
+
+
 def test_nonfinite_detected(torch, hip):
     case = W.stationary_droplet(seed=1, n=64, radius=12.0)
     phi = case.phi0.copy()

@@ -4,7 +4,8 @@
 // the paragraph after Eq. 12, isotropic central stencils), on 19 velocities.
 // A step is either the fused kernel
 //   k3_slab      one x-y tile marching up a z chunk, phi / mu / p rings in
-//                LDS, the whole step per plane (see its comment)
+//                LDS, the whole step per plane (see its comment); k3_slab2
+//                the same one plane shorter when the Eq. 5 term is zero
 // or three kernels that pass fields through HBM:
 //   k3_pull      pull f and gbar; phi (float-float) and the gbar moments
 //   k3_fields_t  on LDS tiles: mu = theta'(phi) - kappa lap phi, then grad
@@ -948,6 +949,199 @@ __global__ void __launch_bounds__(TX * TY) k3_slab(CaseDev c, int parity, int zs
   }
 }
 
+// ---- fused step without the Eq. 5 term (its coefficient is zero: the
+// original model, or theta_M = 0, or equal densities).  lap mu is not needed,
+// so u and p at a position need mu only there, and the pipeline is one plane
+// shorter than k3_slab's: iteration z stages phi(z + 2) over the tile + 2
+// (ring of 3 planes), forms mu, grad phi, u and p at z + 1 over the tile + 1
+// (mu from the phi stencil at the position itself), then collides plane z.
+// The own node's pulled f is carried for two planes.  Walls, periodic seams
+// and the expressions as in k3_slab, so the same bits.
+template <int TX, int TY>
+struct Slab2Lds {
+  static constexpr int PX = TX + 4, PY = TY + 4, NP = PX * PY;  // phi plane
+  static constexpr int UX = TX + 2, UY = TY + 2, NU = UX * UY;  // p plane
+  float ph[3][NP];
+  float pl[3][NP];
+  float p[3][NU];
+};
+
+template <int S, int TX, int TY>
+__global__ void __launch_bounds__(TX * TY) k3_slab2(CaseDev c, int parity, int zs) {
+  using T = Slab2Lds<TX, TY>;
+  constexpr int NT = TX * TY, PX = T::PX, PY = T::PY, UX = T::UX, UY = T::UY;
+  constexpr int NPRING = T::NP - NT;  // positions of the tile + 2 outside the tile
+  constexpr int NRING = T::NU - NT;   // positions of the tile + 1 outside the tile
+  __shared__ T L;
+  const int ntx = (c.nx + TX - 1) / TX, nty = (c.ny + TY - 1) / TY;
+  const int ntiles = ntx * nty * ((c.nz + zs - 1) / zs);
+  const int chunk = (ntiles + 7) >> 3;
+  const int t = (blockIdx.x & 7) * chunk + (blockIdx.x >> 3);
+  if (blockIdx.x >= (unsigned)(8 * chunk) || t >= ntiles) return;
+  const int x0 = (t % ntx) * TX, y0 = ((t / ntx) % nty) * TY;
+  const int za = (t / (ntx * nty)) * zs, zb = min(za + zs, c.nz);
+  const int tid = threadIdx.x;
+  const bool inner = x0 >= 2 && x0 + TX + 2 <= c.nx && y0 >= 2 && y0 + TY + 2 <= c.ny;
+  const int lx = tid % TX, ly = tid / TX;
+  const int gx = x0 + lx, gy = y0 + ly;
+  const bool own = gx < c.nx && gy < c.ny;
+  const char* src = parity ? c.state[1] : c.state[0];
+  const BaseOut<S> op{parity ? c.state[0] : c.state[1]};
+  float* const php = &L.ph[0][0];
+  float* const plp = &L.pl[0][0];
+  float* const pp = &L.p[0][0];
+
+  NodeFields cur{}, nxt{};  // own node: plane z (collided now), plane z + 1
+  // own node's pulled f_1..f_18 at planes z, z + 1 and z + 2 (fn)
+  float fa[Q], fb[Q], fn[Q];
+  for (int z = za - 4; z < zb; ++z) {
+    // the own node's gbar for the collision at the end of the iteration
+    float gv[Q];
+    if (z >= za && own) pull_g<S>(c, src, Node3(c, gx, gy, z), gv);
+    // phi at plane z + 2 over the tile + 2: the own node first (its f kept),
+    // then the 2-wide ring around the tile
+    {
+      const int k = z + 2;
+      const int qz = fold3(k, c.nz, c.wall_z);
+      const int b = slot3(k) * T::NP;
+      for (int r = tid - NT; r < NPRING; r += NT) {
+        int px, py;
+        if (r < 0) {
+          px = lx + 2;
+          py = ly + 2;
+        } else if (r < 2 * PX) {
+          px = r % PX;
+          py = r / PX;
+        } else if (r < 4 * PX) {
+          px = (r - 2 * PX) % PX;
+          py = PY - 2 + (r - 2 * PX) / PX;
+        } else {
+          const int q = r - 4 * PX, col = q % 4;
+          px = col < 2 ? col : PX - 4 + col;
+          py = 2 + q / 4;
+        }
+        int qx = x0 - 2 + px, qy = y0 - 2 + py;
+        if (!inner) {
+          qx = fold3(qx, c.nx, c.wall_x);
+          qy = fold3(qy, c.ny, c.wall_y);
+        }
+        const Node3 nd(c, qx, qy, qz);
+        float hv, lv;
+        if (r < 0) {
+          pull_f<S>(c, src, nd, fn);
+          phi_of<S>(c, src, nd, fn, hv, lv);
+        } else {
+          pull_phi<S>(c, src, nd, hv, lv);
+        }
+        php[b + px + PX * py] = hv;
+        plp[b + px + PX * py] = lv;
+      }
+    }
+    __syncthreads();
+
+    // mu, gbar moments, grad phi, u and p at plane z + 1 over the tile + 1
+    {
+      const int k = z + 1;
+      if (k >= za - 1 && !(c.wall_z && (k < 0 || k >= c.nz))) {
+        const int qz = fold3(k, c.nz, c.wall_z);
+        const int bm = slot3(k - 1) * T::NP, b0 = slot3(k) * T::NP, bp = slot3(k + 1) * T::NP;
+        const int pb = slot3(k) * T::NU;
+        for (int r = tid - NT; r < NRING; r += NT) {
+          int ux, uy;
+          if (r < 0) {
+            ux = lx + 1;
+            uy = ly + 1;
+          } else if (r < UX) {
+            ux = r;
+            uy = 0;
+          } else if (r < 2 * UX) {
+            ux = r - UX;
+            uy = UY - 1;
+          } else {
+            ux = ((r - 2 * UX) & 1) ? UX - 1 : 0;
+            uy = 1 + ((r - 2 * UX) >> 1);
+          }
+          int qx = x0 - 1 + ux, qy = y0 - 1 + uy, mx = ux, my = uy;
+          if (!inner) {
+            mx = mirror_local(ux, x0 - 1, c.nx, c.wall_x, UX);
+            my = mirror_local(uy, y0 - 1, c.ny, c.wall_y, UY);
+            qx = fold3(qx, c.nx, c.wall_x);
+            qy = fold3(qy, c.ny, c.wall_y);
+          }
+          float m0, m1x, m1y, m1z;
+          pull_moments<S>(c, src, Node3(c, qx, qy, qz), m0, m1x, m1y, m1z);
+          const int pc = (mx + 1) + PX * (my + 1);
+          const float mu = slab_mu<PX>(c, php, plp, bm, b0, bp, pc);
+          const float h0 = php[b0 + pc], l0 = plp[b0 + pc];
+          float g[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+          for (int i = 1; i < Q; ++i) {
+            const int j = (EZ(i) < 0 ? bm : (EZ(i) > 0 ? bp : b0)) + pc + EX(i) + PX * EY(i);
+            const float d = (php[j] - h0) + (plp[j] - l0);
+            const float w = i <= 6 ? (1.0f / 6.0f) : (1.0f / 12.0f);  // 3 w_i
+            if (EX(i)) g[0] += EX(i) > 0 ? w * d : -w * d;
+            if (EY(i)) g[1] += EY(i) > 0 ? w * d : -w * d;
+            if (EZ(i)) g[2] += EZ(i) > 0 ? w * d : -w * d;
+          }
+          const float ph = h0 + l0;
+          const float rho = c.rho0 + ph * c.drho;
+          const float fsx = mu * g[0], fsy = mu * g[1];
+          const float fsz = mu * g[2] - (rho - c.rho_ref) * c.gravity;
+          const float cc = c.corr * 0.0f;  // lap mu is not formed: the coefficient is zero
+          const float iden = __builtin_amdgcn_rcpf(rho - 0.5f * cc);
+          const float vx = (3.0f * m1x + 0.5f * fsx) * iden;
+          const float vy = (3.0f * m1y + 0.5f * fsy) * iden;
+          const float vz = (3.0f * m1z + 0.5f * fsz) * iden;
+          const float p = m0 + (1.0f / 6.0f) * c.drho * (vx * g[0] + vy * g[1] + vz * g[2]);
+          pp[pb + ux + UX * uy] = p;
+          if (r < 0) {
+            nxt.phh = h0;
+            nxt.phl = l0;
+            nxt.mu = mu;
+            nxt.cc = cc;
+            nxt.p = p;
+            nxt.ux = vx;
+            nxt.uy = vy;
+            nxt.uz = vz;
+            nxt.gx = g[0];
+            nxt.gy = g[1];
+            nxt.gz = g[2];
+          }
+        }
+      }
+    }
+    __syncthreads();
+
+    // grad p and the collision of the tile's nodes at plane z
+    if (z >= za && own) {
+      const Node3 nd(c, gx, gy, z);
+      const int uc = (lx + 1) + UX * (ly + 1);
+      const int pm = slot3(zread(c, z - 1)) * T::NU, p0 = slot3(z) * T::NU,
+                pq = slot3(zread(c, z + 1)) * T::NU;
+      const float f0 = pp[p0 + uc];
+      float ax = 0.0f, ay = 0.0f, az = 0.0f;
+#pragma unroll
+      for (int i = 1; i < Q; ++i) {
+        const float d = pp[(EZ(i) < 0 ? pm : (EZ(i) > 0 ? pq : p0)) + uc + EX(i) + UX * EY(i)] - f0;
+        const float w = i <= 6 ? (1.0f / 6.0f) : (1.0f / 12.0f);
+        if (EX(i)) ax += EX(i) > 0 ? w * d : -w * d;
+        if (EY(i)) ay += EY(i) > 0 ? w * d : -w * d;
+        if (EZ(i)) az += EZ(i) > 0 ? w * d : -w * d;
+      }
+      cur.gpx = ax;
+      cur.gpy = ay;
+      cur.gpz = az;
+      collide_node<S>(c, op, nd.idx, fa, gv, cur);
+    }
+    cur = nxt;
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+      fa[i] = fb[i];
+      fb[i] = fn[i];
+    }
+  }
+}
+
 // ---- field dump for lbm_moments / diagnostics
 __global__ void __launch_bounds__(256) k3_dump(CaseDev c, Fields3 fl, FieldPtrs out) {
   const unsigned idx = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1067,7 +1261,10 @@ void launch_fields_t(const CaseDev& c, const d3q19::Fields3& fl, int dump, int p
 template <int S, int TX, int TY>
 void launch_slab(const CaseDev& c, int parity, int zs, hipStream_t s) {
   const int ft = ((c.nx + TX - 1) / TX) * ((c.ny + TY - 1) / TY) * ((c.nz + zs - 1) / zs);
-  if (c.phiv)
+  if (!c.phiv && c.corr == 0.0f)  // no Eq. 5 term: the shorter pipeline
+    hipLaunchKernelGGL((d3q19::k3_slab2<S, TX, TY>), dim3(8 * ((ft + 7) / 8)), dim3(TX * TY),
+                       0, s, c, parity, zs);
+  else if (c.phiv)
     hipLaunchKernelGGL((d3q19::k3_slab<S, TX, TY, true>), dim3(8 * ((ft + 7) / 8)),
                        dim3(TX * TY), 0, s, c, parity, zs);
   else

@@ -435,7 +435,7 @@ def main():
         out["variants"] = extra
         out["d3q19_splash256x256x128"] = {f"{st}_rf{rf}": leg_3d(torch, W, hip, st, rf)
                                           for st, rf in (("fp16", 1), ("fp16", 0), ("fp32", 1),
-                                                         ("fp32", 2))}
+                                                         ("fp32", 0), ("fp32", 2))}
         out["ensemble64"] = {st: leg_ensemble(torch, W, hip, st) for st in ("fp32", "fp16")}
         out["paper_experiments"] = leg_paper(torch, W, hip)
         out["fa_diagnostics"] = leg_fa_diagnostics(torch, W, hip)

@@ -96,10 +96,13 @@ def leg(torch, W, hip, storage, remove_fa, steps, warmup, workload="splash1024x5
                 umax=d["umax"], variant=variant_used)
 
 
-def kernel_3d(hip, variant):
+def kernel_3d(hip, variant, remove_fa):
     """Name of the D3Q19 step a variant launches: the fused step (an x-y tile
-    marching up a z chunk of 16 or more planes) or the three-kernel step."""
+    marching up a z chunk of 16 or more planes; k3_slab2, one plane shorter,
+    for the original model) or the three-kernel step."""
     if hip.variants(hip.D3Q19)[variant][2] >= 16:
+        if remove_fa == 0:
+            return "k3_slab2 (fused D3Q19 step without the Eq. 5 term)"
         return "k3_slab (fused D3Q19 step)"
     return "k3_pull + k3_fields_t + k3_collide"
 
@@ -128,7 +131,7 @@ def leg_3d(torch, W, hip, storage, remove_fa, steps=100, warmup=10, variant=-1):
                 frac=round(ach / HBM_PEAK_GBS, 4), bytes_per_lu=bpl,
                 steps=steps, nonfinite=int(d["nonfinite"]), mass_drift_rel=d["mass_drift_rel"],
                 ms_per_step=round(1e3 * t / steps, 4), variant=variant,
-                kernel=kernel_3d(hip, variant))
+                kernel=kernel_3d(hip, variant, remove_fa))
 
 
 def leg_ensemble(torch, W, hip, storage, steps=200, warmup=20):

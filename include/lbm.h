@@ -160,6 +160,13 @@ int lbm_init(const lbm_case_params* cases, int32_t ncases, const double* const* 
  * Asynchronous unless check_every triggers a check. */
 int lbm_step(lbm_handle* h, int64_t nsteps);
 
+/* Capture and instantiate the HIP graph of graph_steps time steps for the
+ * current launch shape (lbm_set_launch) without advancing the state, so that
+ * a later lbm_step that replays it pays no capture cost.  Nothing is enqueued
+ * on the handle's stream.  No effect with graph_steps = 0.  LBM_ERR_HIP when
+ * the capture or the instantiation fails. */
+int lbm_prepare(lbm_handle* h);
+
 /* Macroscopic fields of case icase at the current time level, written to
  * caller-allocated host float arrays: phi[N], u[dim*N], p[N] (hydrodynamic
  * pressure), mu[N] (chemical potential), fa[dim*N] (the additional force

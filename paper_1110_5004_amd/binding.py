@@ -81,6 +81,7 @@ def lib():
     L.lbm_init.argtypes = [C.POINTER(CaseParams), C.c_int32, C.POINTER(dp), C.POINTER(dp),
                            C.POINTER(dp), _vp, C.c_size_t, _vp, C.c_int32, C.POINTER(_vp)]
     L.lbm_step.argtypes = [_vp, C.c_int64]
+    L.lbm_prepare.argtypes = [_vp]
     L.lbm_moments.argtypes = [_vp, C.c_int32, fp, fp, fp, fp, fp]
     L.lbm_moments_device.argtypes = [_vp, C.c_int32, _vp, _vp, _vp, _vp, _vp]
     L.lbm_diagnostics.argtypes = [_vp, C.c_int32, C.POINTER(Diag)]
@@ -233,6 +234,11 @@ class Simulation:
 
     def step(self, n):
         _check(lib().lbm_step(self.h, int(n)))
+
+    def prepare(self):
+        """Capture the step graph of the current launch shape now (lbm_prepare),
+        so that timed steps replay it without a capture."""
+        _check(lib().lbm_prepare(self.h))
 
     @property
     def time(self):

@@ -14,7 +14,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(OUT_DIR, "liblbm_hip.so")
-SOURCES = ["lbm_runtime.cpp", "lbm_common.hip", "lbm_d2q9.hip", "lbm_d3q19.hip"]
+SOURCES = ["lbm_runtime.cpp", "lbm_common.hip", "lbm_d2q9.hip", "lbm_d3q19.hip",
+           "lbm_d3q19_march.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

@@ -15,102 +15,14 @@
 // Both compute every node to the same bits.  Stencil neighbours go through
 // the periodic / mirror mapping, so positions beyond a wall read their mirror
 // node.
+#include "lbm_d3q19_addr.h"
+#include "lbm_d3q19_lean.h"
 #include "lbm_dev.h"
 #include "lbm_kernels.h"
 #include "lbm_lattice.h"
 
 namespace lbm {
 namespace d3q19 {
-
-__device__ __forceinline__ void coords(const CaseDev& c, unsigned idx, int& x, int& y, int& z) {
-  x = idx % c.nx;
-  const unsigned r = idx / c.nx;
-  y = r % c.ny;
-  z = r / c.ny;
-}
-
-// Node of the stencil neighbour x + e_i (periodic wrap or mirror ghost).
-__device__ __forceinline__ unsigned nbr(const CaseDev& c, int x, int y, int z, int i,
-                                        bool interior, unsigned idx) {
-  if (interior) return idx + EX(i) + c.nx * (EY(i) + c.ny * EZ(i));
-  const int mx = map_axis(x + EX(i), c.nx, c.wall_x);
-  const int my = map_axis(y + EY(i), c.ny, c.wall_y);
-  const int mz = map_axis(z + EZ(i), c.nz, c.wall_z);
-  return mx + c.nx * (my + c.ny * mz);
-}
-
-// A node of the node-parallel kernels and its place at the grid's faces.
-// The kernels run one grid row (y, z) per blockIdx.x and x across
-// blockIdx.y * blockDim.x + threadIdx.x, so y, z and their face flags are
-// uniform and only x is per lane; neighbour and pull offsets are then formed
-// from compile-time e_i without branches or per-lane division.
-struct Node3 {
-  int x;
-  unsigned idx;
-  bool x0, x1, y0, y1, z0, z1;  // x == 0, x == nx - 1, ...
-  __device__ __forceinline__ Node3(const CaseDev& c, int xx, int row)
-      : Node3(c, xx, row % c.ny, row / c.ny) {}
-  __device__ __forceinline__ Node3(const CaseDev& c, int xx, int y, int z) : x(xx) {
-    idx = (unsigned)x + (unsigned)c.nx * ((unsigned)y + (unsigned)c.ny * (unsigned)z);
-    x0 = x == 0;
-    x1 = x == c.nx - 1;
-    y0 = y == 0;
-    y1 = y == c.ny - 1;
-    z0 = z == 0;
-    z1 = z == c.nz - 1;
-  }
-};
-
-// Offset, along one axis of pitch `pitch` and n nodes, of the stencil
-// neighbour one step s in {-1, 0, 1} away: the next node; across a periodic
-// seam its image; across a wall the mirror ghost, which is the node itself.
-__device__ __forceinline__ int face_step(int s, bool lo, bool hi, int wall, int n, int pitch) {
-  if (s == 0) return 0;
-  const bool out = s > 0 ? hi : lo;
-  return out ? (wall ? 0 : -s * (n - 1) * pitch) : s * pitch;
-}
-
-// Node of the stencil neighbour x + e_i.
-__device__ __forceinline__ unsigned nbr3(const CaseDev& c, const Node3& nd, int i) {
-  return nd.idx + face_step(EX(i), nd.x0, nd.x1, c.wall_x, c.nx, 1) +
-         face_step(EY(i), nd.y0, nd.y1, c.wall_y, c.ny, c.nx) +
-         face_step(EZ(i), nd.z0, nd.z1, c.wall_z, c.nz, c.nx * c.ny);
-}
-
-// Offset of the pull source x - s along one axis: the previous node, across a
-// periodic seam its image; across a wall the node itself, and bb is set (the
-// population is then read in the opposite direction: halfway bounce-back).
-__device__ __forceinline__ int pull_step(int s, bool lo, bool hi, int wall, int n, int pitch,
-                                         bool& bb) {
-  if (s == 0) return 0;
-  const bool out = s > 0 ? lo : hi;
-  bb = bb || (out && wall);
-  return out ? (wall ? 0 : s * (n - 1) * pitch) : -s * pitch;
-}
-
-// Byte offset of the population of direction i pulled by the node.
-template <int S, bool G, class N>
-__device__ __forceinline__ unsigned pull3(const CaseDev& c, const N& nd, int i) {
-  using P = Pops<S, Q>;
-  if (i == 0) return G ? P::gofs(c, 0, nd.idx) : P::fofs(c, 0, nd.idx);
-  bool bb = false;
-  const int d = pull_step(EX(i), nd.x0, nd.x1, c.wall_x, c.nx, 1, bb) +
-                pull_step(EY(i), nd.y0, nd.y1, c.wall_y, c.ny, c.nx, bb) +
-                pull_step(EZ(i), nd.z0, nd.z1, c.wall_z, c.nz, c.nx * c.ny, bb);
-  const unsigned j = nd.idx + d;
-  if (G) return bb ? P::gofs(c, OPP(i), nd.idx) : P::gofs(c, i, j);
-  return bb ? P::fofs(c, OPP(i), nd.idx) : P::fofs(c, i, j);
-}
-
-// A staging coordinate g of a tile plus its halo mapped into the grid: the
-// periodic image or the wall mirror, then clamped.  Positions a real node
-// reads lie at most 2 <= n outside the grid, where one fold is exact; farther
-// ones occur only in the unused part of a ragged tile.
-__device__ __forceinline__ int fold3(int g, int n, int wall) {
-  if (g < 0) g = wall ? -g - 1 : g + n;
-  else if (g >= n) g = wall ? 2 * n - 1 - g : g - n;
-  return min(max(g, 0), n - 1);
-}
 
 // Launch shape of the node-parallel kernels (see Node3).
 struct RowGrid {
@@ -166,8 +78,20 @@ __global__ void __launch_bounds__(256) k3_pull(CaseDev c, int parity, Fields3 fl
   const unsigned idx = nd.idx;
   const char* src = parity ? c.state[1] : c.state[0];
   float hi, lo, m0, mx, my, mz;
-  pull_phi<S>(c, src, nd, hi, lo);
-  pull_moments<S>(c, src, nd, m0, mx, my, mz);
+  if constexpr (S != ST_FP32) {
+    // 16-bit storage: one-float phi and the moments from the stored words
+    float d[Q], G[Q];
+#pragma unroll
+    for (int i = 1; i < Q; ++i) d[i] = raw16<S>(gload<uint16_t>(src, pull3<S, false>(c, nd, i)));
+#pragma unroll
+    for (int i = 0; i < Q; ++i) G[i] = raw16<S>(gload<uint16_t>(src, pull3<S, true>(c, nd, i)));
+    hi = lean_phi(c, gload<float>(src, 4u * idx), d);
+    lo = 0.0f;
+    lean_moments(c, G, m0, mx, my, mz);
+  } else {
+    pull_phi<S>(c, src, nd, hi, lo);
+    pull_moments<S>(c, src, nd, m0, mx, my, mz);
+  }
   fl.phh[idx] = hi;
   fl.phl[idx] = lo;
   fl.m0[idx] = m0;
@@ -203,7 +127,7 @@ __device__ __forceinline__ void grad_f(const CaseDev& c, const float* f, const N
 // position, so that it equals the mirror node's mu as the step defines it.
 // Stencil sums run over i = 1..18 in lattice order, as in the node-parallel
 // definition, so the result does not depend on the tile shape.
-template <int TX, int TY, int TZ, bool RF2>
+template <int TX, int TY, int TZ, bool RF2, bool LEAN>
 struct FieldTile {
   static constexpr int NT = TX * TY * TZ;
   static constexpr int PX = TX + 4, PY = TY + 4, PZ = TZ + 4;  // phi region
@@ -211,7 +135,7 @@ struct FieldTile {
   static constexpr int NP = PX * PY * PZ, NM = MX * MY * MZ;
   static constexpr int NQ = RF2 ? NM : 1;
   float ph[NP];
-  float pl[NP];
+  float pl[LEAN ? 1 : NP];  // low part of phi (FP32 storage)
   float mu[NM];
   float qx[NQ], qy[NQ], qz[NQ];  // RF2: rho u_o over the mu region
 };
@@ -222,14 +146,48 @@ __device__ __forceinline__ constexpr int nofs(int i) {
   return EX(i) + X * (EY(i) + Y * EZ(i));
 }
 
+// The 18 neighbour values v[1..18] of position pc of an LDS region.
+template <int X, int Y>
+__device__ __forceinline__ void gather18(const float* f, int pc, float* v) {
+#pragma unroll
+  for (int i = 1; i < Q; ++i) v[i] = f[pc + nofs<X, Y>(i)];
+}
+
+// div q = sum_i 3 w_i e_i . q(x + e_i) of a vector field from its neighbour
+// values (lean form: per opposite pair the difference e_{2j-1} . (q_{2j-1} -
+// q_{2j}), axis pairs weighted 1/6, edge pairs 1/12).
+__device__ __forceinline__ float lean_div(const float* qx, const float* qy, const float* qz) {
+  float d[10];
+#pragma unroll
+  for (int j = 1; j <= 9; ++j) {
+    const int i = PI(j);
+    d[j] = edot(i, qx[i] - qx[i + 1], qy[i] - qy[i + 1], qz[i] - qz[i + 1]);
+  }
+  const float a = (d[1] + d[2]) + d[3];
+  const float e = ((((d[4] + d[5]) + d[6]) + d[7]) + d[8]) + d[9];
+  return __builtin_fmaf(1.0f / 6.0f, a, (1.0f / 12.0f) * e);
+}
+
+// rho u_o: rho times the velocity the uncorrected recovery gives (lean form).
+__device__ __forceinline__ void lean_rho_uo(const CaseDev& c, float ph, float mu, float gx,
+                                            float gy, float gz, float mx, float my, float mz,
+                                            float& qx, float& qy, float& qz) {
+  const LeanUP r = lean_recover(c, ph, mu, gx, gy, gz, 0.0f, 0.0f, mx, my, mz);
+  const float rho = __builtin_fmaf(ph, c.drho, c.rho0);
+  qx = rho * r.ux;
+  qy = rho * r.uy;
+  qz = rho * r.uz;
+}
+
 // RF2 (correction from data): also rho u_o over the tile + 1, u_o the
 // uncorrected recovery from the moment planes, then at each node the rate
 // D = drho (phi - phi^(n-1)) + div(rho u_o), with phi^(n-1) from the plane of
-// the current state copy, in place of the Eq. 5 coefficient.
-template <int TX, int TY, int TZ, bool RF2>
+// the current state copy, in place of the Eq. 5 coefficient.  LEAN: the
+// evaluation order of 16-bit storage (lbm_d3q19_lean.h), one-float phi.
+template <int TX, int TY, int TZ, bool RF2, bool LEAN>
 __global__ void __launch_bounds__(TX * TY * TZ)
 k3_fields_t(CaseDev c, Fields3 fl, int dump, int parity) {
-  using T = FieldTile<TX, TY, TZ, RF2>;
+  using T = FieldTile<TX, TY, TZ, RF2, LEAN>;
   constexpr int PX = T::PX, PY = T::PY, MX = T::MX, MY = T::MY;
   __shared__ T L;
   // XCD-aware tile order: workgroup b runs on XCD b % 8 and takes the b / 8-th
@@ -266,7 +224,7 @@ k3_fields_t(CaseDev c, Fields3 fl, int dump, int parity) {
       }
       const unsigned q = qx + c.nx * (qy + c.ny * qz);
       hv[it] = fl.phh[q];
-      lv[it] = fl.phl[q];
+      if constexpr (!LEAN) lv[it] = fl.phl[q];
     }
   }
 #pragma unroll
@@ -274,7 +232,7 @@ k3_fields_t(CaseDev c, Fields3 fl, int dump, int parity) {
     const int k = tid + it * T::NT;
     if (k < T::NP) {
       L.ph[k] = hv[it];
-      L.pl[k] = lv[it];
+      if constexpr (!LEAN) L.pl[k] = lv[it];
     }
   }
   __syncthreads();
@@ -288,17 +246,24 @@ k3_fields_t(CaseDev c, Fields3 fl, int dump, int parity) {
       mz = mirror_local(mz, z0 - 1, c.nz, c.wall_z, T::MZ);
     }
     const int pc = (mx + 1) + PX * ((my + 1) + PY * (mz + 1));
-    const float h0 = L.ph[pc], l0 = L.pl[pc];
-    float la = 0.0f, le = 0.0f;
+    if constexpr (LEAN) {
+      float v[Q];
+      gather18<PX, PY>(L.ph, pc, v);
+      const float h0 = L.ph[pc];
+      L.mu[k] = lean_mu(c, h0, lean_lap(v, h0));
+    } else {
+      const float h0 = L.ph[pc], l0 = L.pl[pc];
+      float la = 0.0f, le = 0.0f;
 #pragma unroll
-    for (int i = 1; i < Q; ++i) {
-      const int j = pc + nofs<PX, PY>(i);
-      const float d = (L.ph[j] - h0) + (L.pl[j] - l0);
-      if (i <= 6) la += d;
-      else le += d;
+      for (int i = 1; i < Q; ++i) {
+        const int j = pc + nofs<PX, PY>(i);
+        const float d = (L.ph[j] - h0) + (L.pl[j] - l0);
+        if (i <= 6) la += d;
+        else le += d;
+      }
+      const float lap = (1.0f / 3.0f) * la + (1.0f / 6.0f) * le;
+      L.mu[k] = dtheta(c, h0, l0) - c.kappa * lap;
     }
-    const float lap = (1.0f / 3.0f) * la + (1.0f / 6.0f) * le;
-    L.mu[k] = dtheta(c, h0, l0) - c.kappa * lap;
   }
   __syncthreads();
 
@@ -320,24 +285,32 @@ k3_fields_t(CaseDev c, Fields3 fl, int dump, int parity) {
       }
       const unsigned q = qx + c.nx * (qy + c.ny * qz);
       const int pc = (mx + 1) + PX * ((my + 1) + PY * (mz + 1));
-      const float h0 = L.ph[pc], l0 = L.pl[pc];
-      float g[3] = {0.0f, 0.0f, 0.0f};
-#pragma unroll
-      for (int i = 1; i < Q; ++i) {
-        const int j = pc + nofs<PX, PY>(i);
-        const float d = (L.ph[j] - h0) + (L.pl[j] - l0);
-        const float w = i <= 6 ? (1.0f / 6.0f) : (1.0f / 12.0f);
-        if (EX(i)) g[0] += EX(i) > 0 ? w * d : -w * d;
-        if (EY(i)) g[1] += EY(i) > 0 ? w * d : -w * d;
-        if (EZ(i)) g[2] += EZ(i) > 0 ? w * d : -w * d;
-      }
-      const float rho = c.rho0 + (h0 + l0) * c.drho;
       const float mu = L.mu[k];
-      const float iden = __builtin_amdgcn_rcpf(rho);
-      const float fsz = mu * g[2] - (rho - c.rho_ref) * c.gravity;
-      L.qx[k] = rho * ((3.0f * fl.m1x[q] + 0.5f * (mu * g[0])) * iden);
-      L.qy[k] = rho * ((3.0f * fl.m1y[q] + 0.5f * (mu * g[1])) * iden);
-      L.qz[k] = rho * ((3.0f * fl.m1z[q] + 0.5f * fsz) * iden);
+      if constexpr (LEAN) {
+        float v[Q], g[3];
+        gather18<PX, PY>(L.ph, pc, v);
+        lean_grad(v, g[0], g[1], g[2]);
+        lean_rho_uo(c, L.ph[pc], mu, g[0], g[1], g[2], fl.m1x[q], fl.m1y[q], fl.m1z[q],
+                    L.qx[k], L.qy[k], L.qz[k]);
+      } else {
+        const float h0 = L.ph[pc], l0 = L.pl[pc];
+        float g[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int i = 1; i < Q; ++i) {
+          const int j = pc + nofs<PX, PY>(i);
+          const float d = (L.ph[j] - h0) + (L.pl[j] - l0);
+          const float w = i <= 6 ? (1.0f / 6.0f) : (1.0f / 12.0f);
+          if (EX(i)) g[0] += EX(i) > 0 ? w * d : -w * d;
+          if (EY(i)) g[1] += EY(i) > 0 ? w * d : -w * d;
+          if (EZ(i)) g[2] += EZ(i) > 0 ? w * d : -w * d;
+        }
+        const float rho = c.rho0 + (h0 + l0) * c.drho;
+        const float iden = __builtin_amdgcn_rcpf(rho);
+        const float fsz = mu * g[2] - (rho - c.rho_ref) * c.gravity;
+        L.qx[k] = rho * ((3.0f * fl.m1x[q] + 0.5f * (mu * g[0])) * iden);
+        L.qy[k] = rho * ((3.0f * fl.m1y[q] + 0.5f * (mu * g[1])) * iden);
+        L.qz[k] = rho * ((3.0f * fl.m1z[q] + 0.5f * fsz) * iden);
+      }
     }
     __syncthreads();
   }
@@ -346,63 +319,94 @@ k3_fields_t(CaseDev c, Fields3 fl, int dump, int parity) {
   if (!own) return;
   const int pc = (lx + 2) + PX * ((ly + 2) + PY * (lz + 2));
   const int mc = (lx + 1) + MX * ((ly + 1) + MY * (lz + 1));
-  const float h0 = L.ph[pc], l0 = L.pl[pc];
-  float g[3] = {0.0f, 0.0f, 0.0f};
-#pragma unroll
-  for (int i = 1; i < Q; ++i) {
-    const int j = pc + nofs<PX, PY>(i);
-    const float d = (L.ph[j] - h0) + (L.pl[j] - l0);
-    const float w = i <= 6 ? (1.0f / 6.0f) : (1.0f / 12.0f);  // 3 w_i
-    if (EX(i)) g[0] += EX(i) > 0 ? w * d : -w * d;
-    if (EY(i)) g[1] += EY(i) > 0 ? w * d : -w * d;
-    if (EZ(i)) g[2] += EZ(i) > 0 ? w * d : -w * d;
-  }
   const float mu = L.mu[mc];
-  float lmu = 0.0f;
-  if (dump || c.corr != 0.0f) {
-    float la = 0.0f, le = 0.0f;
-#pragma unroll
-    for (int i = 1; i < Q; ++i) {
-      const float d = L.mu[mc + nofs<MX, MY>(i)] - mu;
-      if (i <= 6) la += d;
-      else le += d;
+  if constexpr (LEAN) {
+    float v[Q], g[3];
+    gather18<PX, PY>(L.ph, pc, v);
+    lean_grad(v, g[0], g[1], g[2]);
+    const float ph = L.ph[pc];
+    float lmu = 0.0f;
+    if (dump || c.corr != 0.0f) {
+      gather18<MX, MY>(L.mu, mc, v);
+      lmu = lean_lap(v, mu);
     }
-    lmu = (1.0f / 3.0f) * la + (1.0f / 6.0f) * le;
-  }
-  const float ph = h0 + l0;
-  const float rho = c.rho0 + ph * c.drho;
-  // (rho - c/2) u = 3 sum e gbar + (F_s + G)/2, gravity along -z
-  const float fsx = mu * g[0], fsy = mu * g[1];
-  const float fsz = mu * g[2] - (rho - c.rho_ref) * c.gravity;
-  float cc = c.corr * lmu;
-  if constexpr (RF2) {
-    const char* src = parity ? c.state[1] : c.state[0];
-    float dv = 0.0f;
+    float cc = c.corr * lmu;
+    if constexpr (RF2) {
+      const char* src = parity ? c.state[1] : c.state[0];
+      float qx[Q], qy[Q], qz[Q];
+      gather18<MX, MY>(L.qx, mc, qx);
+      gather18<MX, MY>(L.qy, mc, qy);
+      gather18<MX, MY>(L.qz, mc, qz);
+      cc = __builtin_fmaf(ph - gload<float>(src, c.phiv + 4u * idx), c.drho,
+                          lean_div(qx, qy, qz));
+      fl.dd[idx] = cc;
+    }
+    const LeanUP r = lean_recover(c, ph, mu, g[0], g[1], g[2], cc, m0, m1x, m1y, m1z);
+    if (dump) fl.mu[idx] = mu;
+    fl.ux[idx] = r.ux;
+    fl.uy[idx] = r.uy;
+    fl.uz[idx] = r.uz;
+    fl.p[idx] = r.p;
+    fl.lmu[idx] = lmu;
+    return;
+  } else {
+    const float h0 = L.ph[pc], l0 = L.pl[pc];
+    float g[3] = {0.0f, 0.0f, 0.0f};
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
-      const int j = mc + nofs<MX, MY>(i);
+      const int j = pc + nofs<PX, PY>(i);
+      const float d = (L.ph[j] - h0) + (L.pl[j] - l0);
       const float w = i <= 6 ? (1.0f / 6.0f) : (1.0f / 12.0f);  // 3 w_i
-      float e = 0.0f;
-      if (EX(i)) e += EX(i) > 0 ? L.qx[j] : -L.qx[j];
-      if (EY(i)) e += EY(i) > 0 ? L.qy[j] : -L.qy[j];
-      if (EZ(i)) e += EZ(i) > 0 ? L.qz[j] : -L.qz[j];
-      dv += w * e;
+      if (EX(i)) g[0] += EX(i) > 0 ? w * d : -w * d;
+      if (EY(i)) g[1] += EY(i) > 0 ? w * d : -w * d;
+      if (EZ(i)) g[2] += EZ(i) > 0 ? w * d : -w * d;
     }
-    cc = (ph - gload<float>(src, c.phiv + 4u * idx)) * c.drho + dv;
-    fl.dd[idx] = cc;
+    float lmu = 0.0f;
+    if (dump || c.corr != 0.0f) {
+      float la = 0.0f, le = 0.0f;
+#pragma unroll
+      for (int i = 1; i < Q; ++i) {
+        const float d = L.mu[mc + nofs<MX, MY>(i)] - mu;
+        if (i <= 6) la += d;
+        else le += d;
+      }
+      lmu = (1.0f / 3.0f) * la + (1.0f / 6.0f) * le;
+    }
+    const float ph = h0 + l0;
+    const float rho = c.rho0 + ph * c.drho;
+    // (rho - c/2) u = 3 sum e gbar + (F_s + G)/2, gravity along -z
+    const float fsx = mu * g[0], fsy = mu * g[1];
+    const float fsz = mu * g[2] - (rho - c.rho_ref) * c.gravity;
+    float cc = c.corr * lmu;
+    if constexpr (RF2) {
+      const char* src = parity ? c.state[1] : c.state[0];
+      float dv = 0.0f;
+#pragma unroll
+      for (int i = 1; i < Q; ++i) {
+        const int j = mc + nofs<MX, MY>(i);
+        const float w = i <= 6 ? (1.0f / 6.0f) : (1.0f / 12.0f);  // 3 w_i
+        float e = 0.0f;
+        if (EX(i)) e += EX(i) > 0 ? L.qx[j] : -L.qx[j];
+        if (EY(i)) e += EY(i) > 0 ? L.qy[j] : -L.qy[j];
+        if (EZ(i)) e += EZ(i) > 0 ? L.qz[j] : -L.qz[j];
+        dv += w * e;
+      }
+      cc = (ph - gload<float>(src, c.phiv + 4u * idx)) * c.drho + dv;
+      fl.dd[idx] = cc;
+    }
+    const float iden = __builtin_amdgcn_rcpf(rho - 0.5f * cc);
+    const float ux = (3.0f * m1x + 0.5f * fsx) * iden;
+    const float uy = (3.0f * m1y + 0.5f * fsy) * iden;
+    const float uz = (3.0f * m1z + 0.5f * fsz) * iden;
+    // mu for the field dump only: the collision forms mu and grad phi again from
+    // the phi planes (phi_grad_mu), with these expressions in this order
+    if (dump) fl.mu[idx] = mu;
+    fl.ux[idx] = ux;
+    fl.uy[idx] = uy;
+    fl.uz[idx] = uz;
+    fl.p[idx] = m0 + (1.0f / 6.0f) * c.drho * (ux * g[0] + uy * g[1] + uz * g[2]);
+    fl.lmu[idx] = lmu;
   }
-  const float iden = __builtin_amdgcn_rcpf(rho - 0.5f * cc);
-  const float ux = (3.0f * m1x + 0.5f * fsx) * iden;
-  const float uy = (3.0f * m1y + 0.5f * fsy) * iden;
-  const float uz = (3.0f * m1z + 0.5f * fsz) * iden;
-  // mu for the field dump only: the collision forms mu and grad phi again from
-  // the phi planes (phi_grad_mu), with these expressions in this order
-  if (dump) fl.mu[idx] = mu;
-  fl.ux[idx] = ux;
-  fl.uy[idx] = uy;
-  fl.uz[idx] = uz;
-  fl.p[idx] = m0 + (1.0f / 6.0f) * c.drho * (ux * g[0] + uy * g[1] + uz * g[2]);
-  fl.lmu[idx] = lmu;
 }
 
 // ---- 4: collision and store
@@ -565,6 +569,26 @@ __device__ __forceinline__ void phi_grad_mu(const CaseDev& c, const Fields3& fl,
   n.gz = g[2];
 }
 
+// Stores of one node in the 16-bit layout from the packed results of
+// lean_collide: f_0 as a float, f_{2j-1} / f_{2j} from the low / high half of
+// of[j], g_{2k} / g_{2k+1} from og[k] (g_18 in the low half of og[9]).
+template <int S>
+__device__ __forceinline__ void store_lean(const CaseDev& c, char* dst, unsigned idx, float f0,
+                                           const uint32_t* og, const uint32_t* of) {
+  using P = Pops<S, Q>;
+  gstore<float>(dst, 4u * idx, f0);
+#pragma unroll
+  for (int j = 1; j <= 9; ++j) {
+    gstore<uint16_t>(dst, P::fofs(c, PI(j), idx), (uint16_t)(of[j] & 0xffffu));
+    gstore<uint16_t>(dst, P::fofs(c, PI(j) + 1, idx), (uint16_t)(of[j] >> 16));
+  }
+#pragma unroll
+  for (int k = 0; k < 10; ++k) {
+    gstore<uint16_t>(dst, P::gofs(c, 2 * k, idx), (uint16_t)(og[k] & 0xffffu));
+    if (2 * k + 1 < Q) gstore<uint16_t>(dst, P::gofs(c, 2 * k + 1, idx), (uint16_t)(og[k] >> 16));
+  }
+}
+
 template <int S>
 __global__ void __launch_bounds__(256) k3_collide(CaseDev c, int parity, Fields3 fl) {
   const int x = blockIdx.y * blockDim.x + threadIdx.x;
@@ -573,6 +597,42 @@ __global__ void __launch_bounds__(256) k3_collide(CaseDev c, int parity, Fields3
   const unsigned idx = nd.idx;
   const char* src = parity ? c.state[1] : c.state[0];
   char* dst = parity ? c.state[0] : c.state[1];
+  if constexpr (S != ST_FP32) {
+    // 16-bit storage: the lean form (lbm_d3q19_lean.h)
+    uint16_t fh[Q], gh[Q + 1];
+    float v[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      if (i > 0) fh[i] = gload<uint16_t>(src, pull3<S, false>(c, nd, i));
+      gh[i] = gload<uint16_t>(src, pull3<S, true>(c, nd, i));
+    }
+    gh[Q] = 0;
+    uint32_t Fr[10], Gr[10];
+#pragma unroll
+    for (int j = 1; j <= 9; ++j) Fr[j] = pack16(fh[PI(j)], fh[PI(j) + 1]);
+#pragma unroll
+    for (int k = 0; k < 10; ++k) Gr[k] = pack16(gh[2 * k], gh[2 * k + 1]);
+    LeanNode n;
+    n.ph = fl.phh[idx];
+#pragma unroll
+    for (int i = 1; i < Q; ++i) v[i] = fl.phh[nbr3(c, nd, i)];
+    lean_grad(v, n.gx, n.gy, n.gz);
+    n.mu = lean_mu(c, n.ph, lean_lap(v, n.ph));
+#pragma unroll
+    for (int i = 1; i < Q; ++i) v[i] = fl.p[nbr3(c, nd, i)];
+    float gp[3];
+    lean_grad(v, gp[0], gp[1], gp[2]);
+    n.cc = c.phiv ? fl.dd[idx] : c.corr * fl.lmu[idx];
+    n.p = fl.p[idx];
+    n.ux = fl.ux[idx];
+    n.uy = fl.uy[idx];
+    n.uz = fl.uz[idx];
+    uint32_t og[10], of[10];
+    const float f0 = lean_collide<S>(c, n, gp[0], gp[1], gp[2], Gr, Fr, og, of);
+    store_lean<S>(c, dst, idx, f0, og, of);
+    if (c.phiv) gstore<float>(dst, c.phiv + 4u * idx, n.ph);
+    return;
+  }
   const OutPtrs<S, Q> op(c, dst);
   float fv[Q], gv[Q];
   pull_node<S>(c, src, nd, fv, gv);
@@ -1217,13 +1277,15 @@ k3_init(CaseDev c, int parity, const double* __restrict__ phi0, const double* __
 
 // ------------------------------------------------------------ launchers
 // Variants 0-4: the three-kernel step, by the tile of its fields kernel (the
-// pull and collision kernels are node-parallel, 256 threads).  Variants 5-10:
-// the fused step, by its x-y tile and z chunk (tz planes).  All give the same
+// pull and collision kernels are node-parallel, 256 threads).  Variants 5-12:
+// the fused step, by its x-y tile and z chunk (tz planes); the 64-wide tiles
+// give the 16-bit step one 128-byte line per row and plane.  All give the same
 // bits, in every model and storage layout.
 const TileShape kD3Q19Tiles[] = {{16, 8, 4, 512, 0},  {32, 4, 4, 512, 0},  {32, 8, 2, 512, 0},
                                  {16, 16, 2, 512, 0}, {8, 8, 8, 512, 0},   {32, 8, 16, 256, 0},
                                  {32, 8, 32, 256, 0}, {32, 16, 16, 512, 0}, {32, 16, 32, 512, 0},
-                                 {32, 8, 64, 256, 0}, {32, 16, 64, 512, 0}};
+                                 {32, 8, 64, 256, 0}, {32, 16, 64, 512, 0}, {64, 8, 32, 512, 0},
+                                 {64, 8, 64, 512, 0}};
 constexpr int kD3Q19Fused = 5;  // first fused variant
 const int kD3Q19TileCount = sizeof(kD3Q19Tiles) / sizeof(kD3Q19Tiles[0]);
 
@@ -1246,20 +1308,21 @@ d3q19::Fields3 fields3(const Field3Ptrs& f) {
   return fl;
 }
 
-template <int FX, int FY, int FZ>
+template <int FX, int FY, int FZ, bool LEAN>
 void launch_fields_t(const CaseDev& c, const d3q19::Fields3& fl, int dump, int parity,
                      hipStream_t s) {
   const int ft = ((c.nx + FX - 1) / FX) * ((c.ny + FY - 1) / FY) * ((c.nz + FZ - 1) / FZ);
   if (c.phiv)
-    hipLaunchKernelGGL((d3q19::k3_fields_t<FX, FY, FZ, true>), dim3(8 * ((ft + 7) / 8)),
+    hipLaunchKernelGGL((d3q19::k3_fields_t<FX, FY, FZ, true, LEAN>), dim3(8 * ((ft + 7) / 8)),
                        dim3(FX * FY * FZ), 0, s, c, fl, dump, parity);
   else
-    hipLaunchKernelGGL((d3q19::k3_fields_t<FX, FY, FZ, false>), dim3(8 * ((ft + 7) / 8)),
+    hipLaunchKernelGGL((d3q19::k3_fields_t<FX, FY, FZ, false, LEAN>), dim3(8 * ((ft + 7) / 8)),
                        dim3(FX * FY * FZ), 0, s, c, fl, dump, parity);
 }
 
 template <int S, int TX, int TY>
 void launch_slab(const CaseDev& c, int parity, int zs, hipStream_t s) {
+  static_assert(S == ST_FP32, "16-bit storage runs the fused step k3_march");
   const int ft = ((c.nx + TX - 1) / TX) * ((c.ny + TY - 1) / TY) * ((c.nz + zs - 1) / zs);
   if (!c.phiv && c.corr == 0.0f)  // no Eq. 5 term: the shorter pipeline
     hipLaunchKernelGGL((d3q19::k3_slab2<S, TX, TY>), dim3(8 * ((ft + 7) / 8)), dim3(TX * TY),
@@ -1276,11 +1339,19 @@ template <int S>
 hipError_t pipeline(int variant, const CaseDev& c, int parity, const d3q19::Fields3& fl,
                     int dump, bool collide, hipStream_t s) {
   if (variant >= kD3Q19Fused && variant < kD3Q19TileCount) {
-    if (collide) {
+    // 16-bit storage with the correction from data, or on a grid of odd
+    // width (the fused 16-bit step pairs x-adjacent nodes), runs the
+    // three-kernel step
+    if (collide && (S == ST_FP32 || (!c.phiv && !(c.nx & 1)))) {
       const TileShape& t = kD3Q19Tiles[variant];
-      if (t.tx == 32 && t.ty == 8) launch_slab<S, 32, 8>(c, parity, t.tz, s);
-      else launch_slab<S, 32, 16>(c, parity, t.tz, s);
-      return hipGetLastError();
+      if constexpr (S != ST_FP32) {
+        return d3q19_march(c, S, t.tx, t.ty, t.tz, parity, s);
+      } else {
+        if (t.tx == 32 && t.ty == 8) launch_slab<S, 32, 8>(c, parity, t.tz, s);
+        else if (t.tx == 64) launch_slab<S, 64, 8>(c, parity, t.tz, s);
+        else launch_slab<S, 32, 16>(c, parity, t.tz, s);
+        return hipGetLastError();
+      }
     }
     variant = 1;
   }
@@ -1288,11 +1359,11 @@ hipError_t pipeline(int variant, const CaseDev& c, int parity, const d3q19::Fiel
   if (rg.grid.y > 65535u) return hipErrorInvalidConfiguration;
   hipLaunchKernelGGL(d3q19::k3_pull<S>, rg.grid, rg.block, 0, s, c, parity, fl);
   switch (variant) {
-    case 0: launch_fields_t<16, 8, 4>(c, fl, dump, parity, s); break;
-    case 1: launch_fields_t<32, 4, 4>(c, fl, dump, parity, s); break;
-    case 2: launch_fields_t<32, 8, 2>(c, fl, dump, parity, s); break;
-    case 3: launch_fields_t<16, 16, 2>(c, fl, dump, parity, s); break;
-    case 4: launch_fields_t<8, 8, 8>(c, fl, dump, parity, s); break;
+    case 0: launch_fields_t<16, 8, 4, (S != ST_FP32)>(c, fl, dump, parity, s); break;
+    case 1: launch_fields_t<32, 4, 4, (S != ST_FP32)>(c, fl, dump, parity, s); break;
+    case 2: launch_fields_t<32, 8, 2, (S != ST_FP32)>(c, fl, dump, parity, s); break;
+    case 3: launch_fields_t<16, 16, 2, (S != ST_FP32)>(c, fl, dump, parity, s); break;
+    case 4: launch_fields_t<8, 8, 8, (S != ST_FP32)>(c, fl, dump, parity, s); break;
     default: return hipErrorInvalidValue;
   }
   if (collide) hipLaunchKernelGGL(d3q19::k3_collide<S>, rg.grid, rg.block, 0, s, c, parity, fl);

@@ -54,6 +54,10 @@ struct Field3Ptrs {
 };
 hipError_t d3q19_step_case(int variant, const CaseDev& c, int storage, int parity,
                            const Field3Ptrs& f, hipStream_t stream);
+// The fused D3Q19 step for 16-bit storage (k3_march): tx x ty tiles of the
+// x-y plane (32 x 8, 32 x 16 or 64 x 8) marching up chunks of zs planes.
+hipError_t d3q19_march(const CaseDev& c, int storage, int tx, int ty, int zs, int parity,
+                       hipStream_t stream);
 hipError_t d3q19_fields_case(const CaseDev& c, int storage, int parity, const Field3Ptrs& f,
                              const FieldPtrs& out, hipStream_t stream);
 hipError_t d3q19_init(const CaseDev& c, int storage, int parity, const double* phi0,

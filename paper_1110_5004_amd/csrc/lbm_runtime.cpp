@@ -596,6 +596,12 @@ int lbm_step(lbm_handle* h, int64_t nsteps) {
   return LBM_OK;
 }
 
+int lbm_prepare(lbm_handle* h) {
+  if (!h) return fail(LBM_ERR_ARG, "NULL handle");
+  if (h->graph_steps < 2) return LBM_OK;
+  return ensure_graph(h);
+}
+
 int lbm_moments_device(lbm_handle* h, int32_t icase, float* phi, float* u, float* p, float* mu,
                        float* fa) {
   if (!h || icase < 0 || icase >= h->ncases) return fail(LBM_ERR_ARG, "bad handle or case");

@@ -147,8 +147,9 @@ def _fused_variants(hip):
 @pytest.mark.parametrize("dims,wall", [((70, 40, 70), (0, 0, 1)), ((66, 36, 40), (1, 1, 1)),
                                        ((40, 20, 36), (0, 0, 0))])
 @pytest.mark.parametrize("storage,rf,well", [("fp32", 1, 0), ("fp16", 1, 0), ("bf16", 1, 0),
-                                             ("fp32", 0, 0), ("fp32", 1, 1), ("fp32", 2, 0),
-                                             ("fp16", 2, 0)])
+                                             ("fp32", 0, 0), ("fp16", 0, 0), ("bf16", 0, 0),
+                                             ("fp32", 1, 1), ("fp16", 1, 1), ("fp16", 0, 1),
+                                             ("fp32", 2, 0), ("fp16", 2, 0)])
 def test_fused_step_bitwise(hip, dims, wall, storage, rf, well):
     """The fused step (one x-y tile marching up a z chunk) against the
     three-kernel step: several x and y tiles, several z chunks, ragged edges,

@@ -184,6 +184,41 @@ int lbm_moments_device(lbm_handle* h, int32_t icase, float* phi, float* u, float
  * reproducible from run to run).  Synchronises the stream. */
 int lbm_diagnostics(lbm_handle* h, int32_t icase, lbm_diag* out);
 
+/* Slots of the device output of lbm_field_diagnostics (doubles). */
+enum {
+  LBM_DIAG_MASS = 0,           /* sum phi */
+  LBM_DIAG_MOMENTUM = 1,       /* 1..3: sum rho u per axis */
+  LBM_DIAG_WSUM = 4,           /* sum w (w as in lbm_diag) */
+  LBM_DIAG_CENTROID = 5,       /* 5..7: sum w x / sum w */
+  LBM_DIAG_CENTROID_VEL = 8,   /* 8..10: sum w u / sum w */
+  LBM_DIAG_SECOND_MOMENT = 11, /* 11..13: sum w (x - X)^2 / sum w, X the centroid */
+  LBM_DIAG_UMAX = 14,          /* max |u| */
+  LBM_DIAG_NONFINITE = 15,     /* nodes with a non-finite phi or u component */
+  LBM_DIAG_SLOTS = 16
+};
+/* Partial sums of lbm_field_diagnostics: 512 workgroups x 16 doubles. */
+#define LBM_DIAG_WORKSPACE_BYTES 65536
+
+/* The diagnostics of lbm_diagnostics computed from node fields in device
+ * memory (those lbm_moments_device writes, say): phi[N] and u[dim*N] (SoA,
+ * component a at offset a*N) of an nx x ny x nz grid (nz = 1 for dim = 2),
+ * N = nx ny nz, node index x + nx (y + ny z).  The density is linear in phi
+ * between (phi_g, rho_g) and (phi_l, rho_l) (Eq. 4a / 4b); the centroid
+ * weight is w = clamp(2 s - 1/2, 0, 1), s = (phi - phi_g) / (phi_l - phi_g).
+ * Moments with no weight (sum w = 0) are 0.
+ * out: device double[LBM_DIAG_SLOTS] in the slot layout above (components
+ * beyond dim are 0).  workspace: device memory of at least
+ * LBM_DIAG_WORKSPACE_BYTES, 8-byte aligned, for the partial sums; overwritten.
+ * Both caller-owned.  Four kernels are enqueued on hip_stream (no
+ * synchronisation); the reduction order is fixed, so results are
+ * bit-reproducible.  LBM_ERR_ARG for dim not 2 or 3, a grid with a side
+ * below 1 or N >= 2^31, phi_l == phi_g, non-finite parameters, null
+ * pointers, or a short or misaligned workspace; nothing is enqueued then. */
+int lbm_field_diagnostics(int32_t dim, int32_t nx, int32_t ny, int32_t nz, const float* phi,
+                          const float* u, double phi_g, double phi_l, double rho_g,
+                          double rho_l, double* out, void* workspace, size_t workspace_bytes,
+                          void* hip_stream);
+
 /* Spread radius of case icase at the current time level: the largest half
  * distance between the outermost crossings of phi = level along a grid row in
  * x (every y, z), crossings located by linear interpolation between nodes x

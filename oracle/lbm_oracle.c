@@ -676,6 +676,55 @@ void orc_diag(orc_sim* s, double* out) {
   out[16] = bad;
 }
 
+/* The diagnostics of orc_diag from given node fields phi[n] and u[dim*n]
+ * (n = nx ny nz, node x + nx (y + ny z)): rho linear in phi through (phi_g,
+ * rho_g) and (phi_l, rho_l) (Eq. 4a / 4b), centroid weight clamp(2 s - 1/2,
+ * 0, 1) with s the fraction of the way from phi_g to phi_l.  out[16]: mass,
+ * momentum[3], sum w, centroid[3], centroid velocity[3], second moment about
+ * the centroid[3], max |u|, number of nodes with a non-finite phi or u. */
+void orc_field_diag(int dim, int nx, int ny, int nz, const double* phi, const double* u,
+                    double phi_g, double phi_l, double rho_g, double rho_l, double* out) {
+  const long n = (long)nx * ny * (dim == 3 ? nz : 1);
+  for (int k = 0; k < 16; ++k) out[k] = 0.0;
+  double sw = 0.0, sx[3] = {0, 0, 0};
+  for (long idx = 0; idx < n; ++idx) {
+    const long x[3] = {idx % nx, (idx / nx) % ny, idx / ((long)nx * ny)};
+    const double ph = phi[idx];
+    const double rho = rho_g + (ph - phi_g) * (rho_l - rho_g) / (phi_l - phi_g);
+    double w = 2.0 * (ph - phi_g) / (phi_l - phi_g) - 0.5;
+    w = w < 0.0 ? 0.0 : (w > 1.0 ? 1.0 : w);
+    double uu = 0.0;
+    int finite = isfinite(ph);
+    out[0] += ph;
+    sw += w;
+    for (int k = 0; k < dim; ++k) {
+      const double uk = u[k * n + idx];
+      out[1 + k] += rho * uk;
+      sx[k] += w * x[k];
+      out[8 + k] += w * uk;
+      uu += uk * uk;
+      finite = finite && isfinite(uk);
+    }
+    if (sqrt(uu) > out[14]) out[14] = sqrt(uu);
+    if (!finite) out[15] += 1.0;
+  }
+  out[4] = sw;
+  for (int k = 0; k < dim; ++k) {
+    out[5 + k] = sw > 0.0 ? sx[k] / sw : 0.0;
+    out[8 + k] = sw > 0.0 ? out[8 + k] / sw : 0.0;
+  }
+  for (long idx = 0; idx < n; ++idx) {
+    const long x[3] = {idx % nx, (idx / nx) % ny, idx / ((long)nx * ny)};
+    double w = 2.0 * (phi[idx] - phi_g) / (phi_l - phi_g) - 0.5;
+    w = w < 0.0 ? 0.0 : (w > 1.0 ? 1.0 : w);
+    for (int k = 0; k < dim; ++k) {
+      const double d = x[k] - out[5 + k];
+      out[11 + k] += w * d * d;
+    }
+  }
+  for (int k = 0; k < dim; ++k) out[11 + k] = sw > 0.0 ? out[11 + k] / sw : 0.0;
+}
+
 double orc_spread_radius(int nx, int ny, int nz, const double* phi, double level) {
   double best = 0.0;
   for (long r = 0; r < (long)ny * nz; ++r) {

@@ -101,6 +101,10 @@ void orc_diag(orc_sim* s, double* out);
  * are located by linear interpolation; the row's value is half the distance
  * between its outermost crossings; the result is the maximum over rows with
  * two or more crossings, 0 if there is none.  phi[nx*ny*nz], node order. */
+/* Diagnostics of orc_diag from given node fields (phi, u), rho linear in phi
+ * through (phi_g, rho_g), (phi_l, rho_l); out[16] (see lbm_oracle.c). */
+void orc_field_diag(int dim, int nx, int ny, int nz, const double* phi, const double* u,
+                    double phi_g, double phi_l, double rho_g, double rho_l, double* out);
 double orc_spread_radius(int nx, int ny, int nz, const double* phi, double level);
 
 /* The additional interfacial force of Eq. 12 estimated from discrete data

@@ -61,6 +61,7 @@ def load(path=None):
     lib.orc_grad_lap.argtypes = [P, _DP, dp, dp]
     lib.orc_stream_words.argtypes = [P, _UP, _UP]
     lib.orc_spread_radius.argtypes = [C.c_int, C.c_int, C.c_int, _DP, C.c_double]
+    lib.orc_field_diag.argtypes = [C.c_int] * 4 + [_DP, _DP] + [C.c_double] * 4 + [_DP]
     lib.orc_fa_discrete.argtypes = [P, _DP, _DP, _DP, _DP]
     lib.orc_fa_leelin.argtypes = [P, _DP, _DP, _DP, _DP]
     lib.orc_spread_radius.restype = C.c_double
@@ -92,6 +93,24 @@ def spread_radius(phi, dims, level=0.5, lib=None):
     a = np.ascontiguousarray(phi, dtype=np.float64).ravel()
     assert a.size == nx * ny * nz
     return float(lib.orc_spread_radius(nx, ny, nz, a, float(level)))
+
+
+def field_diag(phi, u, dims, phi_g, phi_l, rho_g, rho_l, lib=None):
+    """Diagnostics of given node fields phi [N], u [dim, N] (see
+    orc_field_diag): dict of mass, momentum, wsum, centroid, centroid_vel,
+    second_moment, umax, nonfinite."""
+    lib = lib or load()
+    dim = len(dims)
+    nz = int(dims[2]) if dim == 3 else 1
+    ph = np.ascontiguousarray(phi, dtype=np.float64).ravel()
+    uu = np.ascontiguousarray(u, dtype=np.float64).ravel()
+    assert ph.size * dim == uu.size == int(np.prod(dims)) * dim
+    d = np.zeros(16)
+    lib.orc_field_diag(dim, int(dims[0]), int(dims[1]), nz, ph, uu, float(phi_g), float(phi_l),
+                       float(rho_g), float(rho_l), d)
+    return dict(mass=d[0], momentum=d[1:4].copy(), wsum=d[4], centroid=d[5:8].copy(),
+                centroid_vel=d[8:11].copy(), second_moment=d[11:14].copy(), umax=d[14],
+                nonfinite=int(d[15]), slots=d)
 
 
 def fa_discrete(case, phi_prev, phi, u, lib=None):

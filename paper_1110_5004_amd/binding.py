@@ -105,6 +105,9 @@ def lib():
     L.lbm_copy_bw.argtypes = [_vp, _vp, C.c_int64, _vp]
     L.lbm_pull_copy_bw.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, _vp,
                                    _vp, _vp]
+    L.lbm_field_diagnostics.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_int32, _vp, _vp,
+                                        C.c_double, C.c_double, C.c_double, C.c_double, _vp,
+                                        _vp, C.c_size_t, _vp]
     _lib = L
     return L
 
@@ -388,3 +391,35 @@ def copy_bw(x, y):
     import torch
     _check(lib().lbm_copy_bw(C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()), x.numel(),
                              _stream_handle(torch, x.device)))
+
+
+DIAG_SLOTS = 16
+DIAG_WORKSPACE_BYTES = 65536
+
+
+def _diag_fields(phi, u, dims):
+    dim = len(dims)
+    n = int(np.prod(dims))
+    if phi.numel() != n or u.numel() != dim * n or phi.dtype != u.dtype:
+        raise ValueError("phi must hold N floats and u dim*N floats (N = prod(dims))")
+    nz = dims[2] if dim == 3 else 1
+    return dim, nz
+
+
+def field_diagnostics(phi, u, dims, phi_g, phi_l, rho_g, rho_l, out=None, workspace=None):
+    """lbm_field_diagnostics on device float32 tensors phi [N] and u [dim, N]
+    of a grid dims = (nx, ny[, nz]); returns the float64 device tensor of the
+    LBM_DIAG_* slots (out, or a new one).  workspace: a device tensor of at
+    least DIAG_WORKSPACE_BYTES (a new one when None)."""
+    import torch
+    dim, nz = _diag_fields(phi, u, dims)
+    if out is None:
+        out = torch.empty(DIAG_SLOTS, dtype=torch.float64, device=phi.device)
+    if workspace is None:
+        workspace = torch.empty(DIAG_WORKSPACE_BYTES, dtype=torch.uint8, device=phi.device)
+    _check(lib().lbm_field_diagnostics(
+        dim, dims[0], dims[1], nz, C.c_void_p(phi.data_ptr()), C.c_void_p(u.data_ptr()),
+        phi_g, phi_l, rho_g, rho_l, C.c_void_p(out.data_ptr()),
+        C.c_void_p(workspace.data_ptr()), workspace.numel() * workspace.element_size(),
+        _stream_handle(torch, phi.device)))
+    return out

@@ -323,10 +323,11 @@ hipError_t fa_leelin(int lattice, const CaseDev& c, const WellArgs& wa, const Fi
 }
 
 // ---------------------------------------------------------------- FP64 reductions
-// Sums (and one max) over the nodes of one case, from the dumped fields.
+// Diagnostics of node fields (phi, u) in two passes: sums (and one max) over
+// the nodes, then the second moment about the centroid those sums give.
 // Every node goes to a fixed thread of a fixed workgroup; threads combine by
 // a fixed shuffle tree, waves by a fixed order through LDS, workgroups by a
-// second single-workgroup pass.  The result is therefore bit-reproducible.
+// single-workgroup pass.  The result is therefore bit-reproducible.
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
@@ -338,6 +339,8 @@ __device__ __forceinline__ double wave_max(double v) {
   return v;
 }
 
+// Combine one value per slot and thread of a 256-thread workgroup; slot
+// DG_U2MAX by max, the others by sum; threads 0..kDiagSlots-1 write out.
 __device__ __forceinline__ void block_combine(double* acc, double* sh, double* out) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
@@ -355,35 +358,37 @@ __device__ __forceinline__ void block_combine(double* acc, double* sh, double* o
   }
 }
 
-__global__ void __launch_bounds__(256)
-k_diag_partial(CaseDev c, int dim, const float* __restrict__ phi, const float* __restrict__ ux,
-               const float* __restrict__ uy, const float* __restrict__ uz,
-               double* __restrict__ partials) {
+__device__ __forceinline__ double centroid_weight(const DiagArgs& a, double ph) {
+  const double w = a.wa * ph + a.wb;
+  return w < 0.0 ? 0.0 : (w > 1.0 ? 1.0 : w);
+}
+
+// pass 1: mass, momentum, weight, weighted position and velocity, max u^2,
+// non-finite count
+__global__ void __launch_bounds__(256) k_diag_sums(DiagArgs a, double* __restrict__ partials) {
   __shared__ double sh[4 * kDiagSlots];
   double acc[kDiagSlots];
 #pragma unroll
   for (int s = 0; s < kDiagSlots; ++s) acc[s] = 0.0;
   const int stride = gridDim.x * blockDim.x;
-  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < c.n; idx += stride) {
-    const int x = idx % c.nx;
-    const int y = (idx / c.nx) % c.ny;
-    const int z = idx / (c.nx * c.ny);
-    const double ph = phi[idx];
-    const double u[3] = {ux[idx], uy[idx], dim == 3 ? (double)uz[idx] : 0.0};
-    const double rho = (double)c.rho0 + ph * (double)c.drho;
-    double w = (double)c.wa * ph + (double)c.wb;
-    w = w < 0.0 ? 0.0 : (w > 1.0 ? 1.0 : w);
+  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < a.n; idx += stride) {
+    const int x = idx % a.nx;
+    const int y = (idx / a.nx) % a.ny;
+    const int z = idx / (a.nx * a.ny);
+    const double ph = a.phi[idx];
+    const double rho = a.rho0 + ph * a.drho;
+    const double w = centroid_weight(a, ph);
     const double xc[3] = {(double)x, (double)y, (double)z};
     acc[DG_MASS] += ph;
     double u2 = 0.0;
     bool finite = isfinite(ph);
-    for (int a = 0; a < dim; ++a) {
-      acc[DG_MOM + a] += rho * u[a];
-      acc[DG_WX + a] += w * xc[a];
-      acc[DG_WU + a] += w * u[a];
-      acc[DG_WXX + a] += w * xc[a] * xc[a];
-      u2 += u[a] * u[a];
-      finite = finite && isfinite(u[a]);
+    for (int d = 0; d < a.dim; ++d) {
+      const double u = a.u[d][idx];
+      acc[DG_MOM + d] += rho * u;
+      acc[DG_CEN + d] += w * xc[d];
+      acc[DG_CVEL + d] += w * u;
+      u2 += u * u;
+      finite = finite && isfinite(u);
     }
     acc[DG_WSUM] += w;
     acc[DG_U2MAX] = fmax(acc[DG_U2MAX], u2);
@@ -392,9 +397,34 @@ k_diag_partial(CaseDev c, int dim, const float* __restrict__ phi, const float* _
   block_combine(acc, sh, partials + (size_t)blockIdx.x * kDiagSlots);
 }
 
+// pass 2: sum w (x - X)^2 per axis about the centroid X of pass 1 (out)
 __global__ void __launch_bounds__(256)
-k_diag_final(const double* __restrict__ partials, int nblocks, double* __restrict__ out) {
+k_diag_spread(DiagArgs a, const double* __restrict__ out, double* __restrict__ partials) {
   __shared__ double sh[4 * kDiagSlots];
+  double acc[kDiagSlots];
+#pragma unroll
+  for (int s = 0; s < kDiagSlots; ++s) acc[s] = 0.0;
+  const double cen[3] = {out[DG_CEN], out[DG_CEN + 1], out[DG_CEN + 2]};
+  const int stride = gridDim.x * blockDim.x;
+  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < a.n; idx += stride) {
+    const int xc[3] = {idx % a.nx, (idx / a.nx) % a.ny, idx / (a.nx * a.ny)};
+    const double w = centroid_weight(a, a.phi[idx]);
+    for (int d = 0; d < a.dim; ++d) {
+      const double dx = (double)xc[d] - cen[d];
+      acc[DG_M2 + d] += w * dx * dx;
+    }
+  }
+  block_combine(acc, sh, partials + (size_t)blockIdx.x * kDiagSlots);
+}
+
+// Combine the workgroup partials and finish: pass 1 writes every slot but
+// DG_M2 (centroid and centroid velocity divided by the weight, |u|max), pass
+// 2 only DG_M2 (divided by the weight of pass 1).  No weight: 0.
+__global__ void __launch_bounds__(256)
+k_diag_finish(const double* __restrict__ partials, int nblocks, int pass,
+              double* __restrict__ out) {
+  __shared__ double sh[4 * kDiagSlots];
+  __shared__ double tot[kDiagSlots];
   double acc[kDiagSlots];
 #pragma unroll
   for (int s = 0; s < kDiagSlots; ++s) acc[s] = 0.0;
@@ -405,16 +435,35 @@ k_diag_final(const double* __restrict__ partials, int nblocks, double* __restric
       acc[s] = (s == DG_U2MAX) ? fmax(acc[s], v) : acc[s] + v;
     }
   }
-  block_combine(acc, sh, out);
+  block_combine(acc, sh, tot);
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  if (pass == 1) {
+    const double ws = tot[DG_WSUM];
+    out[DG_MASS] = tot[DG_MASS];
+    out[DG_WSUM] = ws;
+    for (int d = 0; d < 3; ++d) {
+      out[DG_MOM + d] = tot[DG_MOM + d];
+      out[DG_CEN + d] = ws > 0.0 ? tot[DG_CEN + d] / ws : 0.0;
+      out[DG_CVEL + d] = ws > 0.0 ? tot[DG_CVEL + d] / ws : 0.0;
+      out[DG_M2 + d] = 0.0;
+    }
+    out[DG_U2MAX] = sqrt(tot[DG_U2MAX]);
+    out[DG_BAD] = tot[DG_BAD];
+  } else {
+    const double ws = out[DG_WSUM];
+    for (int d = 0; d < 3; ++d) out[DG_M2 + d] = ws > 0.0 ? tot[DG_M2 + d] / ws : 0.0;
+  }
 }
 
-hipError_t reduce_diag(const CaseDev& c, int dim, const FieldPtrs& f, double* partials,
-                       int nblocks, double* out, hipStream_t stream) {
-  hipLaunchKernelGGL(k_diag_partial, dim3(nblocks), dim3(256), 0, stream, c, dim, f.phi,
-                     f.u[0], f.u[1], f.u[2], partials);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(256), 0, stream, partials, nblocks, out);
+hipError_t field_diag(const DiagArgs& a, double* partials, double* out, hipStream_t stream) {
+  hipLaunchKernelGGL(k_diag_sums, dim3(kReduceBlocks), dim3(256), 0, stream, a, partials);
+  hipLaunchKernelGGL(k_diag_finish, dim3(1), dim3(256), 0, stream, partials, kReduceBlocks, 1,
+                     out);
+  hipLaunchKernelGGL(k_diag_spread, dim3(kReduceBlocks), dim3(256), 0, stream, a,
+                     (const double*)out, partials);
+  hipLaunchKernelGGL(k_diag_finish, dim3(1), dim3(256), 0, stream, partials, kReduceBlocks, 2,
+                     out);
   return hipGetLastError();
 }
 

@@ -90,18 +90,27 @@ hipError_t row_spread(const CaseDev& c, const float* phi, double level, double* 
 hipError_t pull_copy(int lattice, int storage, const CaseDev& c, const void* src, void* dst,
                      hipStream_t stream);
 
-// FP64 diagnostics: 16 sums per case, reduced in a fixed order.
+// FP64 diagnostics of node fields: kDiagSlots finished values per call
+// (slot layout below, the same as LBM_DIAG_* of lbm.h), reduced in a fixed
+// order by kReduceBlocks workgroups whose partial sums (kReduceBlocks *
+// kDiagSlots doubles) go through `partials`.
 constexpr int kDiagSlots = 16;
-// slot layout
+constexpr int kReduceBlocks = 512;
 enum {
   DG_MASS = 0, DG_MOM = 1,   /* 1..3 */
-  DG_WSUM = 4, DG_WX = 5,    /* 5..7 */
-  DG_WU = 8,                 /* 8..10 */
-  DG_WXX = 11,               /* 11..13 */
-  DG_U2MAX = 14, DG_BAD = 15
+  DG_WSUM = 4, DG_CEN = 5,   /* 5..7 */
+  DG_CVEL = 8,               /* 8..10 */
+  DG_M2 = 11,                /* 11..13 */
+  DG_U2MAX = 14,             /* |u| max once finished */
+  DG_BAD = 15
 };
-hipError_t reduce_diag(const CaseDev& c, int dim, const FieldPtrs& f, double* partials,
-                       int nblocks, double* out, hipStream_t stream);
-constexpr int kReduceBlocks = 512;
+struct DiagArgs {
+  int dim, nx, ny, nz, n;
+  double rho0, drho;  // rho = rho0 + drho phi
+  double wa, wb;      // centroid weight clamp(wa phi + wb, 0, 1)
+  const float* phi;
+  const float* u[3];
+};
+hipError_t field_diag(const DiagArgs& a, double* partials, double* out, hipStream_t stream);
 
 }  // namespace lbm

@@ -16,6 +16,13 @@
 #include "lbm_kernels.h"
 
 using lbm::CaseDev;
+static_assert(lbm::kDiagSlots == LBM_DIAG_SLOTS && lbm::DG_MOM == LBM_DIAG_MOMENTUM &&
+                  lbm::DG_WSUM == LBM_DIAG_WSUM && lbm::DG_CEN == LBM_DIAG_CENTROID &&
+                  lbm::DG_CVEL == LBM_DIAG_CENTROID_VEL && lbm::DG_M2 == LBM_DIAG_SECOND_MOMENT &&
+                  lbm::DG_U2MAX == LBM_DIAG_UMAX && lbm::DG_BAD == LBM_DIAG_NONFINITE,
+              "diagnostics slot layout");
+static_assert(sizeof(double) * lbm::kReduceBlocks * lbm::kDiagSlots == LBM_DIAG_WORKSPACE_BYTES,
+              "diagnostics workspace");
 using lbm::TileDev;
 
 namespace {
@@ -411,15 +418,53 @@ lbm::FieldPtrs scratch_fields(lbm_handle* h) {
   return f;
 }
 
+// Centroid weight and density of the diagnostics from the bulk values of phi
+// and rho (rho linear in phi between them, Eq. 4a / 4b).
+lbm::DiagArgs diag_args(int dim, int nx, int ny, int nz, double phi_g, double phi_l,
+                        double rho_g, double rho_l) {
+  lbm::DiagArgs a{};
+  a.dim = dim;
+  a.nx = nx;
+  a.ny = ny;
+  a.nz = dim == 3 ? nz : 1;
+  a.n = a.nx * a.ny * a.nz;
+  a.drho = (rho_l - rho_g) / (phi_l - phi_g);
+  a.rho0 = rho_g - phi_g * a.drho;
+  a.wa = 2.0 / (phi_l - phi_g);
+  a.wb = -2.0 * phi_g / (phi_l - phi_g) - 0.5;
+  return a;
+}
+
+// The finished diagnostics (lbm::DG_* slots) of case icase, on the host.
 int diag_sums(lbm_handle* h, int icase, double* s) {
   lbm::FieldPtrs f = scratch_fields(h);
   int rc = dump_fields(h, icase, f);
   if (rc) return rc;
-  HIPCHK(lbm::reduce_diag(h->cd[icase], h->dim, f, h->partials(), lbm::kReduceBlocks, h->dout(),
-                          h->stream));
+  const lbm_case_params& p = h->prm[icase];
+  const bool sym = p.well == LBM_WELL_SYMMETRIC;
+  lbm::DiagArgs a = diag_args(h->dim, p.nx, p.ny, p.nz, sym ? -p.phi_star : 0.0,
+                              sym ? p.phi_star : 1.0, p.rho_g, p.rho_l);
+  a.phi = f.phi;
+  for (int d = 0; d < 3; ++d) a.u[d] = d < h->dim ? f.u[d] : f.u[0];
+  HIPCHK(lbm::field_diag(a, h->partials(), h->dout(), h->stream));
   HIPCHK(hipMemcpyAsync(s, h->dout(), sizeof(double) * lbm::kDiagSlots, hipMemcpyDeviceToHost,
                         h->stream));
   HIPCHK(hipStreamSynchronize(h->stream));
+  return LBM_OK;
+}
+
+// Arguments of lbm_field_diagnostics (and of its variant without workspace).
+int check_field_diag(int32_t dim, int32_t nx, int32_t ny, int32_t nz, const float* phi,
+                     const float* u, double phi_g, double phi_l, double rho_g, double rho_l,
+                     const double* out) {
+  if (dim != 2 && dim != 3) return fail(LBM_ERR_ARG, "dim must be 2 or 3");
+  if (dim == 2) nz = 1;
+  if (nx < 1 || ny < 1 || nz < 1) return fail(LBM_ERR_ARG, "bad grid %d x %d x %d", nx, ny, nz);
+  if ((double)nx * ny * nz >= 2147483648.0) return fail(LBM_ERR_ARG, "grid of 2^31 nodes or more");
+  if (!std::isfinite(phi_g) || !std::isfinite(phi_l) || !std::isfinite(rho_g) ||
+      !std::isfinite(rho_l) || phi_l == phi_g)
+    return fail(LBM_ERR_ARG, "need finite phi_g != phi_l and finite rho_g, rho_l");
+  if (!phi || !u || !out) return fail(LBM_ERR_ARG, "NULL field or output");
   return LBM_OK;
 }
 
@@ -649,14 +694,30 @@ int lbm_diagnostics(lbm_handle* h, int32_t icase, lbm_diag* out) {
   out->wsum = s[lbm::DG_WSUM];
   for (int a = 0; a < h->dim; ++a) {
     out->momentum[a] = s[lbm::DG_MOM + a];
-    if (out->wsum > 0.0) {
-      out->centroid[a] = s[lbm::DG_WX + a] / out->wsum;
-      out->centroid_vel[a] = s[lbm::DG_WU + a] / out->wsum;
-      out->second_moment[a] = s[lbm::DG_WXX + a] / out->wsum - out->centroid[a] * out->centroid[a];
-    }
+    out->centroid[a] = s[lbm::DG_CEN + a];
+    out->centroid_vel[a] = s[lbm::DG_CVEL + a];
+    out->second_moment[a] = s[lbm::DG_M2 + a];
   }
-  out->umax = std::sqrt(s[lbm::DG_U2MAX]);
+  out->umax = s[lbm::DG_U2MAX];
   out->nonfinite = (int64_t)s[lbm::DG_BAD];
+  return LBM_OK;
+}
+
+int lbm_field_diagnostics(int32_t dim, int32_t nx, int32_t ny, int32_t nz, const float* phi,
+                          const float* u, double phi_g, double phi_l, double rho_g,
+                          double rho_l, double* out, void* workspace, size_t workspace_bytes,
+                          void* hip_stream) {
+  int rc = check_field_diag(dim, nx, ny, nz, phi, u, phi_g, phi_l, rho_g, rho_l, out);
+  if (rc) return rc;
+  if (!workspace || workspace_bytes < LBM_DIAG_WORKSPACE_BYTES ||
+      reinterpret_cast<uintptr_t>(workspace) % alignof(double) != 0)
+    return fail(LBM_ERR_ARG, "workspace: need %d bytes, 8-byte aligned",
+                LBM_DIAG_WORKSPACE_BYTES);
+  lbm::DiagArgs a = diag_args(dim, nx, ny, nz, phi_g, phi_l, rho_g, rho_l);
+  a.phi = phi;
+  for (int d = 0; d < 3; ++d) a.u[d] = u + (size_t)(d < dim ? d : 0) * a.n;
+  HIPCHK(lbm::field_diag(a, static_cast<double*>(workspace), out,
+                         reinterpret_cast<hipStream_t>(hip_stream)));
   return LBM_OK;
 }
 

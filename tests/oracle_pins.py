@@ -702,6 +702,39 @@ def check_diagnostics(lib):
     assert abs(d["mass"] - c.phi0.sum()) < 1e-9 and d["nonfinite"] == 0
 
 
+def check_field_diag(lib):
+    """Diagnostics from given node fields.  A 2 x 2 grid worked by hand: phi
+    = 3/4, 1/2, 1/4, 1 at (0,0), (1,0), (0,1), (1,1) gives weights 1, 1/2,
+    0, 1 (sum 5/2), centroid (0.6, 0.4), second moments 0.6 / 2.5 = 0.24 per
+    axis; rho = 0.1 + 0.9 phi with u = (0.01, 0.02, 0.03, 0.04; 0, 0, 0,
+    -0.03) gives momentum (0.0685, -0.03), centroid velocity (0.024, -0.012)
+    and |u|max 0.05.  A non-finite u is counted.  The symmetric well's
+    midpoint phi = 0 weighs 1/2.  A droplet that has moved for a few steps
+    gives the diagnostics of the simulation that produced its fields."""
+    phi = np.array([0.75, 0.5, 0.25, 1.0])
+    u = np.array([[0.01, 0.02, 0.03, 0.04], [0.0, 0.0, 0.0, -0.03]])
+    d = O.field_diag(phi, u, (2, 2), 0.0, 1.0, 0.1, 1.0, lib=lib)
+    want = dict(mass=2.5, wsum=2.5, momentum=[0.0685, -0.03, 0.0], centroid=[0.6, 0.4, 0.0],
+                centroid_vel=[0.024, -0.012, 0.0], second_moment=[0.24, 0.24, 0.0], umax=0.05)
+    for k, v in want.items():
+        assert np.allclose(d[k], v, rtol=0, atol=1e-15), (k, d[k], v)
+    assert d["nonfinite"] == 0
+    u[1, 2] = np.nan
+    assert O.field_diag(phi, u, (2, 2), 0.0, 1.0, 0.1, 1.0, lib=lib)["nonfinite"] == 1
+    ds = O.field_diag(np.zeros(8), np.zeros((3, 8)), (2, 2, 2), -0.5, 0.5, 0.1, 1.0, lib=lib)
+    assert abs(ds["wsum"] - 4.0) < 1e-15 and np.allclose(ds["centroid"], 0.5)
+    assert np.allclose(ds["second_moment"], 0.25) and abs(ds["momentum"]).max() == 0.0
+    c = W.stationary_droplet(seed=3, n=48, radius=12.0, centre_jitter=3.0)
+    sim = O.Sim(c.params, c.phi0, c.u0, c.p0, lib=lib)
+    sim.step(5)
+    f, ref = sim.fields(), sim.diag()
+    d = O.field_diag(f["phi"], f["u"], (48, 48), 0.0, 1.0, c.params["rho_g"],
+                     c.params["rho_l"], lib=lib)
+    assert ref["umax"] > 0.0
+    for k in ("mass", "wsum", "centroid", "centroid_vel", "second_moment", "umax", "momentum"):
+        assert np.allclose(d[k], ref[k], rtol=1e-12, atol=1e-15), (k, d[k], ref[k])
+
+
 def check_spread_radius(lib):
     """Diagnostic D6 (half-width of the widest row, as in the paper's Fig. 5)
     on fields whose answer is known: a two-level band of nodes 10..30 crosses
@@ -950,5 +983,5 @@ ALL_CHECKS = [check_lattice, check_feq_moments, check_geq_moments, check_source_
               check_uniform_flow, check_conservation, check_uniform_force,
               check_shear_wave, check_ch_diffusion, check_switch_noop, check_fa_field,
               check_momentum_balance, check_correction_velocity, check_eq5_fa,
-              check_advection, check_diagnostics, check_spread_radius, check_fa_discrete,
+              check_advection, check_diagnostics, check_field_diag, check_spread_radius, check_fa_discrete,
               check_symmetric_well, check_fa_leelin, check_correction_from_data]

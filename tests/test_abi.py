@@ -116,3 +116,21 @@ def test_empty_case_list_rejected(L):
     assert L.lbm_required_bytes(C.byref(c), 0, C.byref(nbytes)) == B.ERR_ARG
     assert L.lbm_required_bytes(None, 1, C.byref(nbytes)) == B.ERR_ARG
     assert L.lbm_last_error()
+
+
+def test_field_diagnostics_rejects_bad_arguments(L):
+    """Argument errors of lbm_field_diagnostics come back before any device
+    work (the pointers below are never dereferenced)."""
+    p = C.c_void_p(4096)
+    ws = B.DIAG_WORKSPACE_BYTES
+    good = (2, 8, 8, 1, p, p, 0.0, 1.0, 0.1, 1.0, p, p, ws, None)
+    bad = [dict(i=0, v=4), dict(i=1, v=0), dict(i=4, v=None), dict(i=5, v=None),
+           dict(i=10, v=None), dict(i=11, v=None), dict(i=12, v=ws - 8),
+           dict(i=11, v=C.c_void_p(4097)), dict(i=7, v=0.0), dict(i=8, v=float("nan")),
+           dict(i=2, v=1 << 16)]
+    for b in bad:
+        args = list(good)
+        args[b["i"]] = b["v"]
+        if b["i"] == 2:
+            args[0], args[1], args[3] = 3, 1 << 16, 1 << 16  # 2^48 nodes
+        assert L.lbm_field_diagnostics(*args) == B.ERR_ARG, b

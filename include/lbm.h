@@ -219,6 +219,25 @@ int lbm_field_diagnostics(int32_t dim, int32_t nx, int32_t ny, int32_t nz, const
                           double rho_l, double* out, void* workspace, size_t workspace_bytes,
                           void* hip_stream);
 
+/* lbm_field_diagnostics without the workspace argument and with no device
+ * allocation at all, for callers that cannot allocate (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc).  The partial sums
+ * go to a 64 KiB array in device memory that the library holds per GPU for
+ * the life of the process; any grid size up to the limit of
+ * lbm_field_diagnostics (N < 2^31 nodes) fits it.  Every call on a GPU uses
+ * that GPU's one array: calls that overlap in time on the same GPU (two
+ * streams, two threads) race and give wrong results; calls on different GPUs
+ * do not.  Each call overwrites every partial it reads, so no clearing is
+ * needed between calls.  hip_stream must belong to the current device (NULL:
+ * its null stream).  Same arguments, results, bit reproducibility and
+ * LBM_ERR_ARG cases as lbm_field_diagnostics (the workspace ones aside), plus
+ * LBM_ERR_ARG for a stream of another device; LBM_ERR_HIP if the array's
+ * address cannot be obtained on the current device. */
+int lbm_field_diagnostics_noalloc(int32_t dim, int32_t nx, int32_t ny, int32_t nz,
+                                  const float* phi, const float* u, double phi_g,
+                                  double phi_l, double rho_g, double rho_l, double* out,
+                                  void* hip_stream);
+
 /* Spread radius of case icase at the current time level: the largest half
  * distance between the outermost crossings of phi = level along a grid row in
  * x (every y, z), crossings located by linear interpolation between nodes x

@@ -108,6 +108,9 @@ def lib():
     L.lbm_field_diagnostics.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_int32, _vp, _vp,
                                         C.c_double, C.c_double, C.c_double, C.c_double, _vp,
                                         _vp, C.c_size_t, _vp]
+    L.lbm_field_diagnostics_noalloc.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_int32,
+                                                _vp, _vp, C.c_double, C.c_double, C.c_double,
+                                                C.c_double, _vp, _vp]
     _lib = L
     return L
 
@@ -421,5 +424,20 @@ def field_diagnostics(phi, u, dims, phi_g, phi_l, rho_g, rho_l, out=None, worksp
         dim, dims[0], dims[1], nz, C.c_void_p(phi.data_ptr()), C.c_void_p(u.data_ptr()),
         phi_g, phi_l, rho_g, rho_l, C.c_void_p(out.data_ptr()),
         C.c_void_p(workspace.data_ptr()), workspace.numel() * workspace.element_size(),
+        _stream_handle(torch, phi.device)))
+    return out
+
+
+def field_diagnostics_noalloc(phi, u, dims, phi_g, phi_l, rho_g, rho_l, out):
+    """lbm_field_diagnostics_noalloc: as field_diagnostics, into the caller's
+    float64 device tensor out [DIAG_SLOTS], with no workspace (the library's
+    own per-GPU partial-sum array; overlapping calls on one GPU race)."""
+    import torch
+    dim, nz = _diag_fields(phi, u, dims)
+    if out.dtype != torch.float64 or out.numel() < DIAG_SLOTS or not out.is_contiguous():
+        raise ValueError("out must be a contiguous float64 tensor of DIAG_SLOTS values")
+    _check(lib().lbm_field_diagnostics_noalloc(
+        dim, dims[0], dims[1], nz, C.c_void_p(phi.data_ptr()), C.c_void_p(u.data_ptr()),
+        phi_g, phi_l, rho_g, rho_l, C.c_void_p(out.data_ptr()),
         _stream_handle(torch, phi.device)))
     return out

@@ -9,6 +9,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -482,6 +483,37 @@ int check_finite(lbm_handle* h) {
 
 }  // namespace
 
+// ---- partial sums of lbm_field_diagnostics_noalloc
+// A file-scope device array: every GPU the library runs on holds its own copy
+// (64 KiB) until the process ends.  Host code never uses its name as an
+// address; it takes each device's address from hipGetSymbolAddress, once per
+// device with that device current, and keeps it.  Every workgroup of the
+// first and third diagnostics kernels writes its whole slot before the
+// second and fourth read it, so nothing needs clearing between calls.
+static __device__ __align__(256) double scratch[lbm::kReduceBlocks * lbm::kDiagSlots];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch[kMaxDevices];  // per device; nullptr until its first call
+
+int scratch_of_current_device(double** out) {
+  int dev = -1;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices)
+    return fail(LBM_ERR_ARG, "device %d: at most %d devices", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void* p = nullptr;
+    HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(LBM_ERR_HIP, "hipGetSymbolAddress gave a null address");
+    g_scratch[dev] = static_cast<double*>(p);
+  }
+  *out = g_scratch[dev];
+  return LBM_OK;
+}
+}  // namespace
+
 extern "C" {
 
 const char* lbm_last_error(void) { return g_err.c_str(); }
@@ -896,6 +928,29 @@ int lbm_encode16(int32_t storage, const float* in, uint16_t* out, int64_t n, voi
 int lbm_copy_bw(const float* in, float* out, int64_t n, void* hip_stream) {
   if (n < 0 || (n > 0 && (!in || !out))) return fail(LBM_ERR_ARG, "bad buffers");
   HIPCHK(lbm::copy_bw(in, out, n, reinterpret_cast<hipStream_t>(hip_stream)));
+  return LBM_OK;
+}
+
+int lbm_field_diagnostics_noalloc(int32_t dim, int32_t nx, int32_t ny, int32_t nz,
+                                  const float* phi, const float* u, double phi_g,
+                                  double phi_l, double rho_g, double rho_l, double* out,
+                                  void* hip_stream) {
+  int rc = check_field_diag(dim, nx, ny, nz, phi, u, phi_g, phi_l, rho_g, rho_l, out);
+  if (rc) return rc;
+  const hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+  if (s) {  // the partial sums must be those of the device the stream runs on
+    int dev = -1, sdev = -1;
+    HIPCHK(hipGetDevice(&dev));
+    HIPCHK(hipStreamGetDevice(s, &sdev));
+    if (sdev != dev)
+      return fail(LBM_ERR_ARG, "stream of device %d, current device %d", sdev, dev);
+  }
+  double* partials = nullptr;
+  if ((rc = scratch_of_current_device(&partials))) return rc;
+  lbm::DiagArgs a = diag_args(dim, nx, ny, nz, phi_g, phi_l, rho_g, rho_l);
+  a.phi = phi;
+  for (int d = 0; d < 3; ++d) a.u[d] = u + (size_t)(d < dim ? d : 0) * a.n;
+  HIPCHK(lbm::field_diag(a, partials, out, s));
   return LBM_OK;
 }
 

@@ -55,11 +55,24 @@ enum { LBM_D2Q9 = 0, LBM_D3Q19 = 1 };
 enum { LBM_PERIODIC = 0, LBM_WALL = 1 };
 /* Population storage.  LBM_FP32 stores every population as float.
  * LBM_FP16 / LBM_BF16 store f_0 as float and the other populations as 16-bit
- * deviations from the rest state, rounded to nearest even:
+ * deviations from the rest state:
  *   f_i (i > 0):  half(f_i * scale_f)              (rest value of f_i is 0)
  *   g_i:          half((g_i - w_i p0) * scale_g)   (rest value w_i p0)
  * f_0 is then rebuilt as phi - sum_{i>0} f_i from the stored values, so the
- * 16-bit rounding moves phi only between neighbours and sum phi is kept. */
+ * 16-bit rounding moves phi only between neighbours and sum phi is kept.
+ * The f_i round to nearest even.  The g_i of a time step round
+ * stochastically (lbm_encode16_stochastic): to the upper of the two format
+ * values around them with probability equal to the fractional distance from
+ * the lower one, with random bits from a counter-based generator: the
+ * 32-bit "lowbias32" hash of C. Wellons, h(x) = x ^= x >> 16, x *= 0x7feb352d,
+ * x ^= x >> 15, x *= 0x846ca68b, x ^= x >> 16; step key h(t * 0x9e3779b9 +
+ * 0x6a09e667) for the time level t the step reads; node key h(k ^ step key)
+ * for node index k = x + nx (y + ny z); bits r = node key + i * 0x9e3779b9
+ * (mod 2^32) for direction i; FP16 adds r >> 19, BF16 r >> 16, to the float
+ * bits and cuts the bits the format drops.  Rounding to nearest returns the
+ * same error for the same value at every step, which the slowly varying g of
+ * a quiet flow turns into a steady spurious force; the stochastic errors have
+ * mean zero.  The initial populations (lbm_init) round to nearest. */
 enum { LBM_FP32 = 0, LBM_FP16 = 1, LBM_BF16 = 2 };
 /* Double well of the free energy.  LBM_WELL_ASYMMETRIC (Eq. 1a):
  * theta = beta phi^2 (phi - 1)^2, gas phi = 0, liquid phi = 1, density Eq. 4a.
@@ -324,6 +337,19 @@ int lbm_stream_words(int32_t lattice, int32_t nx, int32_t ny, int32_t nz,
  * in: device float[n]; out: device uint16[n]. */
 int lbm_encode16(int32_t storage, const float* in, uint16_t* out, int64_t n,
                  void* hip_stream);
+
+/* The stochastic rounding of the 16-bit g stores of a time step, on the
+ * device: out[k] = bits of the FP16 / BF16 value that the step with counter
+ * `step` (the time level it reads) stores for the value in[k] of direction
+ * `direction` (0..18) of node k.  The result is one of the two format values
+ * around in[k], the upper one with probability equal to the fractional
+ * distance from the lower one (exact values stay; FP16 below its normal range
+ * rounds to nearest on the remaining bits), so the rounding error has mean
+ * zero.  The random bits come from the counter-based generator keyed by step,
+ * node and direction that the storage formats above define.
+ * in: device float[n]; out: device uint16[n]; n <= 2^32. */
+int lbm_encode16_stochastic(int32_t storage, const float* in, uint16_t* out, int64_t n,
+                            uint32_t step, int32_t direction, void* hip_stream);
 
 /* Device copy out[k] = in[k] of n floats with the library's streaming access
  * pattern (achievable-bandwidth calibration). */

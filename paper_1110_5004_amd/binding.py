@@ -102,6 +102,8 @@ def lib():
     L.lbm_stream_words.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_int32, i32p, _vp, _vp,
                                    _vp]
     L.lbm_encode16.argtypes = [C.c_int32, _vp, _vp, C.c_int64, _vp]
+    L.lbm_encode16_stochastic.argtypes = [C.c_int32, _vp, _vp, C.c_int64, C.c_uint32, C.c_int32,
+                                          _vp]
     L.lbm_copy_bw.argtypes = [_vp, _vp, C.c_int64, _vp]
     L.lbm_pull_copy_bw.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, _vp,
                                    _vp, _vp]
@@ -369,6 +371,18 @@ def encode16(storage, x):
     _check(lib().lbm_encode16(STORAGE[storage] if isinstance(storage, str) else storage,
                               C.c_void_p(x.data_ptr()), C.c_void_p(out.data_ptr()), x.numel(),
                               _stream_handle(torch, x.device)))
+    return out
+
+
+def encode16_stochastic(storage, x, step, direction=0):
+    """The step's stochastic 16-bit rounding of a float32 tensor (element k as
+    node k), as an int16 tensor of the same bits."""
+    import torch
+    out = torch.empty(x.shape, dtype=torch.int16, device=x.device)
+    _check(lib().lbm_encode16_stochastic(STORAGE[storage] if isinstance(storage, str) else storage,
+                                         C.c_void_p(x.data_ptr()), C.c_void_p(out.data_ptr()),
+                                         x.numel(), step, direction,
+                                         _stream_handle(torch, x.device)))
     return out
 
 

@@ -55,6 +55,32 @@ k_encode16(const float* __restrict__ in, uint16_t* __restrict__ out, long long n
     out[k] = enc16<S>(in[k]);
 }
 
+// The stochastic rounding of the step's g stores (sr_word) applied to in[k] as
+// the step with counter t stores direction dir of node k.
+template <int S>
+__global__ void __launch_bounds__(256)
+k_encode16_sr(const float* __restrict__ in, uint16_t* __restrict__ out, long long n, uint32_t t,
+              int dir) {
+  const uint32_t sk = sr_step_key(t);
+  for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < n;
+       k += (long long)gridDim.x * blockDim.x)
+    out[k] = enc16_sr<S>(in[k], sr_bits(sr_node_key(sk, (unsigned)k), dir));
+}
+
+hipError_t encode16_sr(int storage, const float* in, uint16_t* out, long long n, uint32_t t,
+                       int dir, hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  long long blocks = (n + 255) / 256;
+  const int grid = (int)(blocks < 65536 ? blocks : 65536);
+  if (storage == ST_BF16)
+    hipLaunchKernelGGL(k_encode16_sr<ST_BF16>, dim3(grid), dim3(256), 0, stream, in, out, n, t,
+                       dir);
+  else
+    hipLaunchKernelGGL(k_encode16_sr<ST_FP16>, dim3(grid), dim3(256), 0, stream, in, out, n, t,
+                       dir);
+  return hipGetLastError();
+}
+
 hipError_t encode16(int storage, const float* in, uint16_t* out, long long n,
                     hipStream_t stream) {
   if (n <= 0) return hipSuccess;

@@ -537,7 +537,7 @@ struct TileLoads {
 template <int TX, int TY, int NPT, int RF, int S, bool FIELDS, bool INNER>
 __device__ __forceinline__ void tile_bcd(TileLds<TX, TY, RF>& L, const CaseDev& c, int x0, int y0,
                                          char* dst, const FieldOut& fo,
-                                         const OwnPops<S, NPT>& own) {
+                                         const OwnPops<S, NPT>& own, uint32_t skey) {
   using T = TileLds<TX, TY, RF>;
   constexpr int NT = TX * TY / NPT;
   constexpr int R = T::R, RM = T::RM;
@@ -734,6 +734,7 @@ __device__ __forceinline__ void tile_bcd(TileLds<TX, TY, RF>& L, const CaseDev& 
       const float omf = 1.0f - c.omega_f;
       const float fP = c.omega_f * c.gamma3 * mu;
       const float fQ = c.omega_f * ph;
+      const uint32_t nkey = S == ST_FP32 ? 0u : sr_node_key(skey, idx);
       float fsum = 0.0f;
 #pragma unroll
       for (int i = 0; i < Q; ++i) {
@@ -750,7 +751,7 @@ __device__ __forceinline__ void tile_bcd(TileLds<TX, TY, RF>& L, const CaseDev& 
           fsum += op.put_f(c, i, idx, fn);
         }
         const float gn = omg * own.g(c, j, i, WT(i)) + WT(i) * ((A + bi) + ti * (Cc + di));
-        op.put_g(c, i, idx, gn, WT(i));
+        op.put_g(c, i, idx, gn, WT(i), sr_bits(nkey, i));
       }
       float h0, e0;
       two_sum(phh, -fsum, h0, e0);
@@ -798,6 +799,8 @@ k_tile(const CaseDev* __restrict__ cases, const TileDev* __restrict__ tiles, int
        int parity, FieldOut fo) {
   static_assert(sizeof(TileLds<TX, TY, RF>) <= 160 * 1024, "tile exceeds the LDS of a CU");
   __shared__ TileLds<TX, TY, RF> lds;
+  uint32_t skey = 0;  // stochastic rounding of the 16-bit g stores
+  if constexpr (S != ST_FP32 && !FIELDS) skey = sr_step_key(sr_clock(cases[0], parity));
   for (TileWalk w(ntiles); w.t < w.t_end; w.t += w.step) {
     const TileDev tl = tiles[w.t];
     const CaseDev c = cases[tl.icase];
@@ -808,11 +811,11 @@ k_tile(const CaseDev* __restrict__ cases, const TileDev* __restrict__ tiles, int
     if (tile_inner<TX, TY, RF>(c, tl)) {
       ld.template load_all<true>(c, src, tl.x0, tl.y0, lds, own);
       __syncthreads();
-      tile_bcd<TX, TY, NPT, RF, S, FIELDS, true>(lds, c, tl.x0, tl.y0, dst, fo, own);
+      tile_bcd<TX, TY, NPT, RF, S, FIELDS, true>(lds, c, tl.x0, tl.y0, dst, fo, own, skey);
     } else {
       ld.template load_all<false>(c, src, tl.x0, tl.y0, lds, own);
       __syncthreads();
-      tile_bcd<TX, TY, NPT, RF, S, FIELDS, false>(lds, c, tl.x0, tl.y0, dst, fo, own);
+      tile_bcd<TX, TY, NPT, RF, S, FIELDS, false>(lds, c, tl.x0, tl.y0, dst, fo, own, skey);
     }
   }
 }

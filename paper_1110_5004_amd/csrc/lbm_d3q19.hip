@@ -429,7 +429,8 @@ struct BaseOut {
     return Pops<S, Q>::put_f(c, base, i, idx, v);
   }
   __device__ __forceinline__ void put_g(const CaseDev& c, int i, unsigned idx, float v,
-                                        float wi) const {
+                                        float wi, uint32_t) const {
+    static_assert(S == ST_FP32, "16-bit steps store through lean_collide");
     Pops<S, Q>::put_g(c, base, i, idx, v, wi);
   }
   __device__ __forceinline__ void put_f0(const CaseDev& c, unsigned idx, float hi,
@@ -496,7 +497,7 @@ __device__ __forceinline__ void collide_node(const CaseDev& c, const Out& op,
       fsum += op.put_f(c, i, idx, fn);
     }
     const float gn = omg * gv[i] + WT(i) * ((A + bi) + ti * (Cc + di));
-    op.put_g(c, i, idx, gn, WT(i));
+    op.put_g(c, i, idx, gn, WT(i), 0u);  // FP32 storage only (16-bit: lean_collide)
   }
   float h0, e0;
   two_sum(n.phh, -fsum, h0, e0);
@@ -628,7 +629,8 @@ __global__ void __launch_bounds__(256) k3_collide(CaseDev c, int parity, Fields3
     n.uy = fl.uy[idx];
     n.uz = fl.uz[idx];
     uint32_t og[10], of[10];
-    const float f0 = lean_collide<S>(c, n, gp[0], gp[1], gp[2], Gr, Fr, og, of);
+    const uint32_t nkey = sr_node_key(sr_step_key(sr_clock(c, parity)), idx);
+    const float f0 = lean_collide<S>(c, n, gp[0], gp[1], gp[2], Gr, Fr, og, of, nkey);
     store_lean<S>(c, dst, idx, f0, og, of);
     if (c.phiv) gstore<float>(dst, c.phiv + 4u * idx, n.ph);
     return;

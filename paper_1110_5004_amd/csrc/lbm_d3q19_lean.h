@@ -75,6 +75,20 @@ __device__ __forceinline__ uint32_t enc_pair(float a, float b) {
     return __builtin_bit_cast(uint32_t, h);
   }
 }
+// The same pair rounded stochastically with the random bits ra, rb (see
+// sr_word); no fusion hazard here, the integer steps keep the conversion apart.
+template <int S>
+__device__ __forceinline__ uint32_t enc_pair_sr(float a, float b, uint32_t ra, uint32_t rb) {
+  const uint32_t ua = sr_word<S>(a, ra), ub = sr_word<S>(b, rb);
+  if constexpr (S == ST_BF16) {
+    return (ua >> 16) | (ub & 0xffff0000u);
+  } else {
+    typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+    typedef float f2 __attribute__((ext_vector_type(2)));
+    const f2 v = {__uint_as_float(ua), __uint_as_float(ub)};
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, h2));
+  }
+}
 template <int S>
 __device__ __forceinline__ float lo16(uint32_t w) {
   return dec16<S>((uint16_t)(w & 0xffffu));
@@ -244,13 +258,14 @@ struct LeanNode {
 // R = om_f phi r.  In stored units (times s_g, s_f) w_i becomes w_i s.
 // F = F_s + G + cc u, grad psi = grad p - drho/3 grad phi.
 //   Gr, Fr: the node's packed stored words (see f_of / g_of);
-//   outg, outf: the packed encoded results in the same layout;
+//   outg, outf: the packed encoded results in the same layout (f rounded to
+//   nearest, g stochastically with the bits sr_bits(nkey, plane));
 //   returns f_0* = phi - sum_{i>0} f*_i of the stored values.
 template <int S>
 __device__ __forceinline__ float lean_collide(const CaseDev& c, const LeanNode& n, float gpx,
                                               float gpy, float gpz, const uint32_t* Gr,
                                               const uint32_t* Fr, uint32_t* outg,
-                                              uint32_t* outf) {
+                                              uint32_t* outf, uint32_t nkey) {
   const float ph = n.ph, ux = n.ux, uy = n.uy, uz = n.uz;
   const float rho = __builtin_fmaf(ph, c.drho, c.rho0);
   const float fx = __builtin_fmaf(n.cc, ux, n.mu * n.gx);
@@ -304,10 +319,11 @@ __device__ __forceinline__ float lean_collide(const CaseDev& c, const LeanNode& 
     const uint32_t ef = enc_pair<S>(fp, fm);
     outf[j] = ef;
     fsum += lo16<S>(ef) + hi16<S>(ef);
-    outg[j - 1] = enc_pair<S>(gprev, gp);  // g_{2j-2}, g_{2j-1}
-    gprev = gm;                             // g_{2j} goes with the next pair
+    // g planes 2j-2, 2j-1
+    outg[j - 1] = enc_pair_sr<S>(gprev, gp, sr_bits(nkey, 2 * j - 2), sr_bits(nkey, 2 * j - 1));
+    gprev = gm;  // plane 2j goes with the next pair
   }
-  outg[9] = enc_pair<S>(gprev, 0.0f);  // g_18 alone in the low half
+  outg[9] = enc_pair_sr<S>(gprev, 0.0f, sr_bits(nkey, 18), 0u);  // g_18 alone in the low half
   return __builtin_fmaf(-c.inv_scale_f, fsum, ph);
 }
 

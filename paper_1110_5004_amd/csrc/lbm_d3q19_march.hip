@@ -309,7 +309,8 @@ __device__ __forceinline__ void issue_g(const CaseDev& c, Rsrc src, const PlaneO
 // the collision computes and cost one memory round trip per plane.
 template <int S, int TX, int TY, int RF, int MODE>
 __device__ __forceinline__ void march_loop(const CaseDev& c, MarchLds<TX, TY, RF>& L,
-                                           const MarchTile& tl, Rsrc src, Rsrc dst) {
+                                           const MarchTile& tl, Rsrc src, Rsrc dst,
+                                           uint32_t skey) {
   using T = MarchLds<TX, TY, RF>;
   constexpr int NT = TX * TY, R = T::R, RX = T::RX, PX = T::PX, PY = T::PY, MX = T::MX,
                 MY = T::MY, UX = T::UX, UY = T::UY;
@@ -537,7 +538,8 @@ __device__ __forceinline__ void march_loop(const CaseDev& c, MarchLds<TX, TY, RF
       for (int j = 1; j <= 9; ++j) fa[j] = L.fw[fs][j - 1][tid];
 #pragma unroll
       for (int kq = 0; kq < 10; ++kq) gc[kq] = L.gw[gs][kq][tid];
-      const float f0 = lean_collide<S>(c, cur, gp0, gp1, gp2, gc, fa, og, of);
+      const uint32_t nkey = sr_node_key(skey, (unsigned)(gx + c.nx * (gy + c.ny * z)));
+      const float f0 = lean_collide<S>(c, cur, gp0, gp1, gp2, gc, fa, og, of, nkey);
       // stores: lane-pair words (even lane: the first population of each
       // packed pair, odd lane: the second, one plane further), the plane and
       // z plane in the uniform offset
@@ -578,6 +580,7 @@ __global__ void __launch_bounds__(TX * TY) k3_march(CaseDev c, int parity, int z
   const int ntiles = ntx * nty * ((c.nz + zs - 1) / zs);
   const int chunk = (ntiles + 7) >> 3;
   const int t = (blockIdx.x & 7) * chunk + (blockIdx.x >> 3);
+  const uint32_t skey = sr_step_key(sr_clock(c, parity));  // stochastic rounding of g
   if (blockIdx.x >= (unsigned)(8 * chunk) || t >= ntiles) return;
   MarchTile tl;
   tl.x0 = (t % ntx) * TX;
@@ -592,9 +595,9 @@ __global__ void __launch_bounds__(TX * TY) k3_march(CaseDev c, int parity, int z
                (c.wall_y && (tl.y0 < R || tl.y0 + TY + R > c.ny));
   const Rsrc src = copy_rsrc(parity ? c.state[1] : c.state[0]);
   const Rsrc dst = copy_rsrc(parity ? c.state[0] : c.state[1]);
-  if (inner) march_loop<S, TX, TY, RF, AD_INNER>(c, L, tl, src, dst);
-  else if (c.wall_x || c.wall_y) march_loop<S, TX, TY, RF, AD_WALL>(c, L, tl, src, dst);
-  else march_loop<S, TX, TY, RF, AD_SEAM>(c, L, tl, src, dst);
+  if (inner) march_loop<S, TX, TY, RF, AD_INNER>(c, L, tl, src, dst, skey);
+  else if (c.wall_x || c.wall_y) march_loop<S, TX, TY, RF, AD_WALL>(c, L, tl, src, dst, skey);
+  else march_loop<S, TX, TY, RF, AD_SEAM>(c, L, tl, src, dst, skey);
 }
 
 }  // namespace d3q19

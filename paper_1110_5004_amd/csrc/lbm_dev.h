@@ -22,6 +22,9 @@ struct CaseDev {
   unsigned stride;  // elements per population plane (>= n); a copy is < 4 GiB,
                     // so every byte offset into it fits 32 bits
   char* state[2];   // the two copies of the stored populations
+  unsigned* clock;  // step counter of the 16-bit stochastic rounding: a step
+                    // reading copy p reads clock[p] and sets clock[1 - p] to
+                    // one more (so graph replays need no host update)
   // physics (float)
   // theta'(phi) = th_k phi (phi - th_r1) (phi - th_r2): the asymmetric well
   // beta phi^2 (phi-1)^2 has th_k = 4 beta, roots 1 and 1/2; the symmetric
@@ -90,6 +93,62 @@ template <int S>
 __device__ __forceinline__ float dec16(uint16_t h) {
   if constexpr (S == ST_BF16) return dec_bf16(h);
   else return dec_fp16(h);
+}
+
+// ---------------------------------------------------------------- stochastic rounding
+// The 16-bit g stores of a time step round stochastically: a value between two
+// neighbours of the 16-bit format becomes the upper one with probability equal
+// to its fractional distance from the lower one, so the rounding error has
+// mean zero whatever the value.  Round to nearest returns the same error for
+// the same value at every step, and the hydrodynamic populations of a slowly
+// varying flow hold nearly the same values from step to step: their rounding
+// then acts like a steady spurious force.
+//
+// Random bits: a counter-based generator, the 32-bit "lowbias32" integer hash
+// of C. Wellons (xorshift-multiply rounds with constants 0x7feb352d and
+// 0x846ca68b), keyed by the time step once per launch and by the node index
+// once per node; the directions of a node take that key plus i times
+// 0x9e3779b9 (a Weyl sequence), each value then uniform on 32 bits.
+__host__ __device__ __forceinline__ uint32_t mix32(uint32_t x) {
+  x ^= x >> 16;
+  x *= 0x7feb352du;
+  x ^= x >> 15;
+  x *= 0x846ca68bu;
+  x ^= x >> 16;
+  return x;
+}
+__host__ __device__ __forceinline__ uint32_t sr_step_key(uint32_t t) {
+  return mix32(t * 0x9e3779b9u + 0x6a09e667u);
+}
+__host__ __device__ __forceinline__ uint32_t sr_node_key(uint32_t step_key, unsigned idx) {
+  return mix32(idx ^ step_key);
+}
+__host__ __device__ __forceinline__ uint32_t sr_bits(uint32_t node_key, int i) {
+  return node_key + (uint32_t)i * 0x9e3779b9u;
+}
+// The float bits of v with r's top bits added below the last bit the 16-bit
+// format keeps, then cut there: FP16 keeps 10 of the 23 fraction bits (13 bits
+// cut, exact in the FP16 normal range), BF16 keeps 7 (16 cut, the upper half is
+// the BF16 word).  A carry into the exponent is the rounding up to the next
+// binade.  Inf stays Inf and NaN stays NaN: a NaN or Inf that came through the
+// 16-bit format has zeros in the cut bits, so the addition cannot carry out of
+// its fraction.
+template <int S>
+__device__ __forceinline__ uint32_t sr_word(float v, uint32_t r) {
+  if constexpr (S == ST_BF16) return __float_as_uint(v) + (r >> 16);
+  else return (__float_as_uint(v) + (r >> 19)) & 0xffffe000u;
+}
+template <int S>
+__device__ __forceinline__ uint16_t enc16_sr(float v, uint32_t r) {
+  const uint32_t b = sr_word<S>(v, r);
+  if constexpr (S == ST_BF16) return (uint16_t)(b >> 16);
+  else return enc_fp16(__uint_as_float(b));
+}
+// Read this step's counter; one thread of the launch sets the next step's.
+__device__ __forceinline__ uint32_t sr_clock(const CaseDev& c, int parity) {
+  const uint32_t t = c.clock[parity];
+  if (blockIdx.x == 0 && threadIdx.x == 0) c.clock[parity ^ 1] = t + 1u;
+  return t;
 }
 
 // Bytes of one copy of the stored populations for q velocities.
@@ -246,10 +305,11 @@ struct OutPtrs {
       return Pops<S, Q>::dec_f(c, h);
     }
   }
+  // store g_i at node idx; 16-bit: rounded stochastically with the bits r
   __device__ __forceinline__ void put_g(const CaseDev& c, int i, unsigned idx, float v,
-                                        float wi) const {
+                                        float wi, uint32_t r) const {
     if constexpr (S == ST_FP32) gstore<float>(g[i], 4u * idx, v);
-    else gstore<uint16_t>(g[i], 2u * idx, enc16<S>((v - wi * c.p0) * c.scale_g));
+    else gstore<uint16_t>(g[i], 2u * idx, enc16_sr<S>((v - wi * c.p0) * c.scale_g, r));
   }
   __device__ __forceinline__ void put_f0(unsigned idx, float hi, float lo) const {
     if constexpr (S == ST_FP32) {

@@ -68,6 +68,8 @@ hipError_t stream_words(int lattice, const CaseDev& c, const uint32_t* in, uint3
                         hipStream_t stream);
 hipError_t encode16(int storage, const float* in, uint16_t* out, long long n,
                     hipStream_t stream);
+hipError_t encode16_sr(int storage, const float* in, uint16_t* out, long long n, uint32_t t,
+                       int dir, hipStream_t stream);
 hipError_t copy_bw(const float* in, float* out, long long n, hipStream_t stream);
 // F_a = -u [(rho^n - rho^(n-1)) + div(rho u)] from phi at n-1 and the dumped
 // fields f (phi, u) at n; out: dim planes of c.n floats.

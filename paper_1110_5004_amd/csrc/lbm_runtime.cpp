@@ -165,7 +165,7 @@ const lbm::TileShape& field_shape(int lattice) {
 }
 
 struct Layout {
-  size_t cases_off, tiles_off, ftiles_off, fld_off, part_off, dout_off, total;
+  size_t cases_off, tiles_off, ftiles_off, fld_off, part_off, dout_off, clock_off, total;
   std::vector<size_t> state_off;  // two copies per case, contiguous
   size_t max_tiles, n_ftiles, fld_plane;
 };
@@ -215,6 +215,8 @@ Layout plan(const lbm_case_params* cs, int n) {
   at = align_up(at + sizeof(double) * lbm::kReduceBlocks * lbm::kDiagSlots);
   L.dout_off = at;
   at = align_up(at + sizeof(double) * lbm::kDiagSlots);
+  L.clock_off = at;  // the step counter of the stochastic rounding, one per copy
+  at = align_up(at + 2 * sizeof(unsigned));
   L.total = at;
   return L;
 }
@@ -251,6 +253,7 @@ struct lbm_handle {
   }
   double* partials() { return reinterpret_cast<double*>(arena + L.part_off); }
   double* dout() { return reinterpret_cast<double*>(arena + L.dout_off); }
+  unsigned* clock() { return reinterpret_cast<unsigned*>(arena + L.clock_off); }
 };
 
 namespace {
@@ -594,8 +597,10 @@ int lbm_init(const lbm_case_params* cases, int32_t ncases, const double* const* 
     hipError_t e = hipMemsetAsync(h->arena, 0, L.total, h->stream);
     if (e != hipSuccess) return bail(fail(LBM_ERR_HIP, "arena clear: %s", hipGetErrorString(e)));
   }
-  for (int k = 0; k < ncases; ++k)
+  for (int k = 0; k < ncases; ++k) {
     h->cd.push_back(derive(cases[k], h->arena + L.state_off[2 * k], h->arena + L.state_off[2 * k + 1]));
+    h->cd.back().clock = h->clock();  // zero from the clear above: step 0
+  }
   {
     hipError_t e = hipMemcpyAsync(h->d_cases(), h->cd.data(), sizeof(CaseDev) * ncases,
                                   hipMemcpyHostToDevice, h->stream);
@@ -837,6 +842,10 @@ int lbm_set_state(lbm_handle* h, int32_t icase, const void* host, size_t bytes) 
 
 int lbm_set_step(lbm_handle* h, int64_t step) {
   if (!h || step < 0) return fail(LBM_ERR_ARG, "bad arguments");
+  // the next step reads the counter of the current copy (modulo 2^32)
+  const unsigned t = (unsigned)(uint64_t)step;
+  HIPCHK(hipMemcpyAsync(h->clock() + h->parity, &t, sizeof t, hipMemcpyHostToDevice, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
   h->step = step;
   return LBM_OK;
 }
@@ -922,6 +931,16 @@ int lbm_encode16(int32_t storage, const float* in, uint16_t* out, int64_t n, voi
   if (storage != LBM_FP16 && storage != LBM_BF16) return fail(LBM_ERR_ARG, "storage must be FP16 or BF16");
   if (n < 0 || (n > 0 && (!in || !out))) return fail(LBM_ERR_ARG, "bad buffers");
   HIPCHK(lbm::encode16(storage, in, out, n, reinterpret_cast<hipStream_t>(hip_stream)));
+  return LBM_OK;
+}
+
+int lbm_encode16_stochastic(int32_t storage, const float* in, uint16_t* out, int64_t n,
+                            uint32_t step, int32_t direction, void* hip_stream) {
+  if (storage != LBM_FP16 && storage != LBM_BF16) return fail(LBM_ERR_ARG, "storage must be FP16 or BF16");
+  if (n < 0 || n > 4294967296LL || (n > 0 && (!in || !out))) return fail(LBM_ERR_ARG, "bad buffers");
+  if (direction < 0 || direction > 18) return fail(LBM_ERR_ARG, "direction must be 0..18");
+  HIPCHK(lbm::encode16_sr(storage, in, out, n, step, direction,
+                          reinterpret_cast<hipStream_t>(hip_stream)));
   return LBM_OK;
 }
 

@@ -5,15 +5,20 @@ tests/golden/falling256x1024_oracle.npz, written by
 tests/golden/make_falling_reference.py from the oracle alone.
 
 Targets for FP16 storage: centroid velocity within 1 % of the oracle's from
-t = 10k on (sampled every 1000 steps), relative mass drift <= 1e-6, and
-max |d phi| <= 1e-3 at the last step.  After 50k steps the droplet has
-fallen ~177 cells and a velocity error of a few 1e-4 (FP32) to 1e-3 (FP16)
-displaces the interface by a fraction of a cell, which alone moves phi by
-~1e-2 across the tanh profile; the raw max |d phi| is therefore reported,
-and the asserted field bound is on the shape: the oracle field shifted by
-the centroid difference (cubic interpolation) against the GPU field.
-BF16 (8-bit mantissa) is measured and reported, with mass conservation and
-finiteness asserted.
+t = 10k on (sampled every 1000 steps), relative mass drift <= 1e-6, and the
+field within 1e-3 at the last step.  The field bound is asserted on the
+shape: the GPU field against the oracle field moved by the centroid
+difference (cubic interpolation).  The raw max |d phi| is reported and held
+to the level of FP32 storage: after 50k steps FP32 arithmetic alone (the
+oracle's own algorithm evaluated in float) leaves the droplet a few hundredths
+of a cell off the FP64 trajectory, and across the tanh profile (slope ~1/4
+per cell) that alone moves phi by ~1e-2, so no FP32-arithmetic path can meet
+a raw 1e-3.  The 16-bit g stores round stochastically; with round to nearest
+the same run drifts a third of a cell and misses the shape bound.
+BF16 (8-bit mantissa, eight times FP16's spacing) is held to bounds eight
+times wider where it has them, with mass conservation and finiteness.
+The droplet's aspect (second moments about the centroid, per axis) is
+compared with the oracle's at the last step.
 """
 import os
 
@@ -45,16 +50,23 @@ def run_falling(hip, storage, ref):
         vel.append(d["centroid_vel"][:2])
         mass.append(d["mass_drift_rel"])
     phi = sim.moments()["phi"].reshape(1024, 256)
-    cen = sim.diagnostics()["centroid"][:2]
+    d = sim.diagnostics()
     sim.close()
-    return phi, np.array(vel), np.array(mass), cen
+    return phi, np.array(vel), np.array(mass), d["centroid"][:2], np.asarray(d["second_moment"][:2])
+
+
+# max centroid-velocity error (from t = 10k), shape error, raw |d phi|, relative
+# error of the second moments at the last step
+BOUNDS = {"fp32": (1e-3, 1e-3, 2e-2, 1e-3),
+          "fp16": (1e-2, 1e-3, 2e-2, 1e-3),
+          "bf16": (1e-2, 8e-3, 1e-1, 8e-3)}
 
 
 @pytest.mark.parametrize("storage", ["fp32", "fp16", "bf16"])
 def test_falling_droplet_50k(hip, storage):
     from scipy.ndimage import shift
     ref = np.load(GOLD)
-    phi, vel, drift, cen = run_falling(hip, storage, ref)
+    phi, vel, drift, cen, m2 = run_falling(hip, storage, ref)
     t = ref["t"][1:]
     late = t >= 10000
     vref = ref["centroid_vel"][1:, 1]
@@ -64,13 +76,46 @@ def test_falling_droplet_50k(hip, storage):
     d = np.asarray(cen) - ref["centroid"][-1]          # (dx, dy) of the GPU droplet
     moved = shift(phi_ref, (d[1], d[0]), order=3, mode="nearest")
     dshape = float(np.abs(phi.astype(np.float64) - moved).max())
+    m2ref = ref["second_moment"][-1][:2]
+    dm2 = float(np.abs(m2 / m2ref - 1.0).max())
+    aspect, aspect_ref = np.sqrt(m2[1] / m2[0]), np.sqrt(m2ref[1] / m2ref[0])
     print(f"falling {storage}: max|dphi|={dphi:.3e} shape error (shifted by "
           f"{d[0]:+.4f},{d[1]:+.4f}) {dshape:.3e} max centroid-velocity error "
-          f"{verr.max():.3e} max mass drift {drift.max():.3e} "
+          f"{verr.max():.3e} max mass drift {drift.max():.3e} second moments "
+          f"{m2[0]:.4f},{m2[1]:.4f} (oracle {m2ref[0]:.4f},{m2ref[1]:.4f}, rel {dm2:.2e}) "
+          f"aspect {aspect:.6f} (oracle {aspect_ref:.6f}) "
           f"(v_ref end {vref[-1]:.4e}, v end {vel[-1, 1]:.4e})")
+    bv, bs, braw, bm2 = BOUNDS[storage]
     assert np.isfinite(phi).all()
     assert drift.max() <= 1e-6
-    if storage == "fp32":
-        assert dshape <= 1e-3 and verr.max() <= 1e-3
-    elif storage == "fp16":
-        assert dshape <= 1e-2 and verr.max() <= 1e-2
+    assert verr.max() <= bv and dshape <= bs and dphi <= braw and dm2 <= bm2
+
+
+@pytest.mark.parametrize("storage", ["fp16", "bf16"])
+def test_rest_pressure_and_scales(hip, storage):
+    """The 16-bit knobs: g stored as deviations from w_i p0, f and g scaled by
+    powers of two.  With p0 the mean initial pressure (the rest pressure of
+    this model is 0 and a droplet adds its Laplace pressure) and other scales,
+    the 128^2 droplet after 1000 steps matches the oracle as closely as with
+    the defaults (for FP16, a power-of-two scale in the normal range changes
+    no rounding; BF16 has the float exponent range and any scale is exact)."""
+    from oracle import oracle as O
+    case = W.stationary_droplet(seed=0, remove_fa=1)
+    ref = O.Sim(case.params, case.phi0, case.u0, case.p0)
+    ref.step(1000)
+    want = ref.fields()
+    k = 1.0 if storage == "fp16" else 8.0
+    errs = []
+    for kw in (dict(), dict(p0=float(np.mean(case.p0)), scale_f=2.0 ** 12, scale_g=2.0 ** 15),
+               dict(p0=float(np.mean(case.p0)), scale_f=2.0 ** 14, scale_g=2.0 ** 12)):
+        sim = hip.Simulation([case], storage=storage, **kw)
+        sim.step(1000)
+        got = sim.moments()
+        drift = sim.diagnostics()["mass_drift_rel"]
+        sim.close()
+        dphi = np.abs(got["phi"] - want["phi"]).max()
+        du = np.linalg.norm(got["u"] - want["u"]) / np.linalg.norm(want["u"])
+        print(f"droplet128 {storage} {kw}: max|dphi|={dphi:.2e} relL2(u)={du:.2e}")
+        assert dphi <= 5e-5 * k and du <= 3e-2 * k and drift <= 1e-6
+        errs.append(du)
+    assert max(errs) <= 3.0 * min(errs)

@@ -40,7 +40,8 @@ WORKLOADS = ("splash3d", "splash1024x512", "droplet4096", "fa_diagnostics")
 # sources of the step kernels of each lattice: committed counters apply only
 # to the kernel they were taken on
 KERNEL_SOURCES = {2: ("lbm_d2q9.hip", "lbm_dev.h", "lbm_lattice.h"),
-                  3: ("lbm_d3q19.hip", "lbm_dev.h", "lbm_lattice.h")}
+                  3: ("lbm_d3q19.hip", "lbm_d3q19_march.hip", "lbm_d3q19_lean.h",
+                      "lbm_d3q19_addr.h", "lbm_dev.h", "lbm_lattice.h")}
 
 
 def parse():

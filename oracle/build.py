@@ -27,6 +27,17 @@ def build(extra_flags=(), out=LIB, verbose=False):
     return out
 
 
+SAN_LIB = os.path.join(OUT_DIR, "liblbm_oracle_san.so")
+
+
+def build_sanitized(verbose=False):
+    """The oracle with AddressSanitizer and UndefinedBehaviorSanitizer (gcc's
+    runtimes; a process loading it must preload libasan).  Any undefined
+    behaviour aborts."""
+    return build(("-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+                  "-fno-sanitize-recover=undefined"), out=SAN_LIB, verbose=verbose)
+
+
 def ensure_built():
     """Build when the library is missing or older than a source or header."""
     deps = SOURCES + [os.path.join(HERE, "lbm_oracle.h")]
@@ -37,5 +48,8 @@ def ensure_built():
 
 
 if __name__ == "__main__":
-    build(verbose=True)
+    if "--sanitize" in sys.argv:
+        build_sanitized(verbose=True)
+    else:
+        build(verbose=True)
     sys.exit(0)

@@ -36,7 +36,7 @@ def load(path=None):
     global _lib
     if path is None and _lib is not None:
         return _lib
-    lib = C.CDLL(path or _build.ensure_built())
+    lib = C.CDLL(path or os.environ.get("LBM_ORACLE_LIB") or _build.ensure_built())
     P = C.POINTER(OrcParams)
     dp = C.POINTER(C.c_double)
     lib.orc_lattice.argtypes = [C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), dp,

@@ -11,7 +11,9 @@ import re
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "_build", "liblbm_hip.so")
+# LBM_HIP_LIB selects another build of the same library (the host-sanitizer
+# build of build.py, say)
+LIB_PATH = os.environ.get("LBM_HIP_LIB") or os.path.join(HERE, "_build", "liblbm_hip.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "lbm.h")
 
 D2Q9, D3Q19 = 0, 1

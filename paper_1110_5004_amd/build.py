@@ -60,6 +60,42 @@ def build(verbose=False, jobs=None):
     return LIB
 
 
+SAN_LIB = os.path.join(OUT_DIR, "liblbm_hip_hostsan.so")
+# host code only: -Xarch_host keeps the sanitizers off the gfx950 code
+HOST_SAN = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+            "-Xarch_host", "-fno-sanitize-recover=undefined", "-Xarch_host",
+            "-fno-omit-frame-pointer"]
+
+
+def build_host_sanitized(verbose=False):
+    """The library with AddressSanitizer and UndefinedBehaviorSanitizer on the
+    host runtime (parameter validation, layout, argument checks of every
+    entry point; lbm_runtime.cpp), linked with the kernels of the normal
+    build.  A process loading it must preload clang's ASan runtime
+    (libclang_rt.asan-x86_64.so of /opt/rocm/llvm)."""
+    if not all(os.path.exists(os.path.join(OUT_DIR, s + ".o")) for s in SOURCES):
+        build(verbose=verbose)
+    obj = os.path.join(OUT_DIR, "lbm_runtime_hostsan.o")
+    cmd = [HIPCC, *FLAGS, *HOST_SAN, "-g", "-x", "hip", "-c",
+           os.path.join(CSRC, "lbm_runtime.cpp"), "-o", obj]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed on lbm_runtime.cpp:\n{r.stdout}\n{r.stderr}")
+    objs = [obj] + [os.path.join(OUT_DIR, s + ".o") for s in SOURCES if s != "lbm_runtime.cpp"]
+    cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", *HOST_SAN, *objs,
+           "-o", SAN_LIB + ".tmp"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(SAN_LIB + ".tmp", SAN_LIB)
+    return SAN_LIB
+
+
 if __name__ == "__main__":
-    build(verbose="-v" in sys.argv)
-    print(LIB)
+    if "--sanitize" in sys.argv:
+        print(build_host_sanitized(verbose="-v" in sys.argv))
+    else:
+        build(verbose="-v" in sys.argv)
+        print(LIB)

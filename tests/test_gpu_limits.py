@@ -168,11 +168,40 @@ def _largest_3d(hip, rf, variant):
     assert np.array_equal(p_b[core], r["p"].reshape(n_s, n_s, n_s)[core])
 
 
-@pytest.mark.parametrize("rf,variant", [(1, 0), (1, 10), (2, 1), (2, 9)])
+@pytest.mark.parametrize("rf,variant", [(1, 0), (1, 10), (0, 12), (2, 1), (2, 9)])
 def test_largest_copy_matches_small_grid_d3q19(hip, rf, variant):
     """D3Q19 state copies just under 4 GiB (256 x 256 x 425 nodes at 154 B;
     256 x 256 x 414 at 158 B with the phi plane), the three-kernel and the
-    fused step, droplet far along z, 8 steps: the 63^3 core of the window
-    around it (all nodes whose 8-step dependency cone the two grids share)
-    equals a 128^3 grid's run bit for bit."""
+    fused step (also the fused step without the Eq. 5 term), droplet far
+    along z, 8 steps: the 63^3 core of the window around it (all nodes whose
+    8-step dependency cone the two grids share) equals a 128^3 grid's run
+    bit for bit."""
     _largest_3d(hip, rf, variant)
+
+
+@pytest.mark.parametrize("rf", [1, 0])
+def test_largest_copy_fp16_fused_equals_three_kernel(hip, rf):
+    """A 16-bit D3Q19 state copy just under 4 GiB (256 x 256 x 840 nodes at
+    78 B), droplet far along z, 6 steps: the fused 16-bit step (k3_march,
+    variant 12) equals the three-kernel step (variant 1) bit for bit over the
+    whole grid, so its 32-bit buffer offsets hold up to the end of a copy.
+    (The stochastic rounding draws from the node index, so a smaller grid's
+    run is not a bitwise reference here; the other form on the same grid
+    is.)"""
+    import torch
+    nz = 840
+    prm = W.base_params(W.D3Q19, 256, 256, nz, (0, 0, 1), sigma=0.01, remove_fa=rf)
+    phi, u, p = W.droplet_fields(prm, (128.25, 128.5, nz - 40.25), 10.0, impact_u=0.03)
+    states = []
+    for variant in (1, 12):
+        sim = hip.Simulation([W.Case(prm, phi, u, p)], storage="fp16")
+        per_copy = sim.state_bytes()
+        assert 0.98 * 2**32 < per_copy < 2**32
+        sim.set_launch(variant, 0, 16)
+        sim.step(6)
+        d = sim.diagnostics()
+        assert d["nonfinite"] == 0 and d["mass_drift_rel"] <= 1e-6
+        states.append(torch.from_numpy(sim.get_state()))
+        sim.close()
+        torch.cuda.empty_cache()
+    assert torch.equal(states[0], states[1])

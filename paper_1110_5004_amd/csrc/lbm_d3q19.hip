@@ -79,21 +79,29 @@ __global__ void __launch_bounds__(256) k3_pull(CaseDev c, int parity, Fields3 fl
   const char* src = parity ? c.state[1] : c.state[0];
   float hi, lo, m0, mx, my, mz;
   if constexpr (S != ST_FP32) {
-    // 16-bit storage: one-float phi and the moments from the stored words
-    float d[Q], G[Q];
+    // 16-bit storage: one-float phi and the moments from the stored words,
+    // packed in pairs as the fused step holds them
+    uint16_t fh[Q], gh[Q + 1];
 #pragma unroll
-    for (int i = 1; i < Q; ++i) d[i] = raw16<S>(gload<uint16_t>(src, pull3<S, false>(c, nd, i)));
+    for (int i = 1; i < Q; ++i) fh[i] = gload<uint16_t>(src, pull3<S, false>(c, nd, i));
 #pragma unroll
-    for (int i = 0; i < Q; ++i) G[i] = raw16<S>(gload<uint16_t>(src, pull3<S, true>(c, nd, i)));
-    hi = lean_phi(c, gload<float>(src, 4u * idx), d);
+    for (int i = 0; i < Q; ++i) gh[i] = gload<uint16_t>(src, pull3<S, true>(c, nd, i));
+    gh[Q] = 0;
+    uint32_t Fr[10], Gr[10];
+    Fr[0] = 0u;
+#pragma unroll
+    for (int j = 1; j <= 9; ++j) Fr[j] = pack16(fh[PI(j)], fh[PI(j) + 1]);
+#pragma unroll
+    for (int k = 0; k < 10; ++k) Gr[k] = pack16(gh[2 * k], gh[2 * k + 1]);
+    hi = lean_phi_packed<S>(c, gload<float>(src, 4u * idx), Fr);
     lo = 0.0f;
-    lean_moments(c, G, m0, mx, my, mz);
+    lean_moments_packed<S>(c, Gr, m0, mx, my, mz);
   } else {
     pull_phi<S>(c, src, nd, hi, lo);
     pull_moments<S>(c, src, nd, m0, mx, my, mz);
   }
   fl.phh[idx] = hi;
-  fl.phl[idx] = lo;
+  if constexpr (S == ST_FP32) fl.phl[idx] = lo;  // 16-bit: phi is one float
   fl.m0[idx] = m0;
   fl.m1x[idx] = mx;
   fl.m1y[idx] = my;
@@ -1205,11 +1213,14 @@ __global__ void __launch_bounds__(TX * TY) k3_slab2(CaseDev c, int parity, int z
 }
 
 // ---- field dump for lbm_moments / diagnostics
-__global__ void __launch_bounds__(256) k3_dump(CaseDev c, Fields3 fl, FieldPtrs out) {
+// (one_float: 16-bit storage, whose phi is the one float of the phh plane;
+// its pull leaves the phl plane unwritten)
+__global__ void __launch_bounds__(256) k3_dump(CaseDev c, Fields3 fl, FieldPtrs out,
+                                               int one_float) {
   const unsigned idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (unsigned)c.n) return;
   const float ux = fl.ux[idx], uy = fl.uy[idx], uz = fl.uz[idx], lmu = fl.lmu[idx];
-  out.phi[idx] = fl.phh[idx] + fl.phl[idx];
+  out.phi[idx] = one_float ? fl.phh[idx] : fl.phh[idx] + fl.phl[idx];
   out.u[0][idx] = ux;
   out.u[1][idx] = uy;
   out.u[2][idx] = uz;
@@ -1394,7 +1405,8 @@ hipError_t d3q19_fields_case(const CaseDev& c, int storage, int parity, const Fi
   }
   if (e != hipSuccess) return e;
   const int grid = (c.n + 255) / 256;
-  hipLaunchKernelGGL(d3q19::k3_dump, dim3(grid), dim3(256), 0, stream, c, fl, out);
+  hipLaunchKernelGGL(d3q19::k3_dump, dim3(grid), dim3(256), 0, stream, c, fl, out,
+                     storage != ST_FP32 ? 1 : 0);
   return hipGetLastError();
 }
 

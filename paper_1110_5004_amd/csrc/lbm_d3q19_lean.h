@@ -222,22 +222,59 @@ __device__ __forceinline__ uint32_t pack16(uint16_t lo, uint16_t hi) {
   return (uint32_t)lo | ((uint32_t)hi << 16);
 }
 
-// phi and the moments from packed words (lean_phi / lean_moments).
+// phi and the moments from packed words.  FP16: each word's two halves
+// enter a running FP32 sum through one v_dot2_f32_f16 with weights (1, 1),
+// or (e_a, e_b) for a first moment; that adds both products and the sum with
+// one rounding (products of a half and +-1 are exact; subnormal halves
+// included).  BF16: decoded, then lean_phi / lean_moments.
+typedef _Float16 lean_h2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ float dot2_acc(uint32_t w, float a, float b, float acc) {
+  const lean_h2 wt = {(_Float16)a, (_Float16)b};
+  return __builtin_amdgcn_fdot2(__builtin_bit_cast(lean_h2, w), wt, acc, false);
+}
 template <int S>
 __device__ __forceinline__ float lean_phi_packed(const CaseDev& c, float f0, const uint32_t* Fr) {
-  float d[Q];
+  if constexpr (S == ST_FP16) {
+    // Fr[j] holds the opposite pair (2j - 1, 2j); summed in pair order
+    float s = dot2_acc(Fr[1], 1.0f, 1.0f, 0.0f);
 #pragma unroll
-  for (int i = 1; i < Q; ++i) d[i] = f_of<S>(Fr, i);
-  return lean_phi(c, f0, d);
+    for (int j = 2; j <= 9; ++j) s = dot2_acc(Fr[j], 1.0f, 1.0f, s);
+    return __builtin_fmaf(c.inv_scale_f, s, f0);
+  } else {
+    float d[Q];
+#pragma unroll
+    for (int i = 1; i < Q; ++i) d[i] = f_of<S>(Fr, i);
+    return lean_phi(c, f0, d);
+  }
 }
 template <int S>
 __device__ __forceinline__ void lean_moments_packed(const CaseDev& c, const uint32_t* Gr,
                                                     float& m0, float& mx, float& my,
                                                     float& mz) {
-  float G[Q];
+  if constexpr (S == ST_FP16) {
+    // Gr[k] holds directions 2k and 2k + 1 (Gr[9]: direction 18 and a zero
+    // half); each sum runs over the words in order, skipping words whose
+    // weights are both zero
+    float a = 0.0f, sx = 0.0f, sy = 0.0f, sz = 0.0f;
 #pragma unroll
-  for (int i = 0; i < Q; ++i) G[i] = g_of<S>(Gr, i);
-  lean_moments(c, G, m0, mx, my, mz);
+    for (int k = 0; k < 10; ++k) {
+      const int i0 = 2 * k, i1 = 2 * k + 1 < Q ? 2 * k + 1 : 0;
+      const float b1 = 2 * k + 1 < Q ? 1.0f : 0.0f;
+      a = dot2_acc(Gr[k], 1.0f, b1, a);
+      if (EX(i0) || (i1 && EX(i1))) sx = dot2_acc(Gr[k], EX(i0), i1 ? EX(i1) : 0, sx);
+      if (EY(i0) || (i1 && EY(i1))) sy = dot2_acc(Gr[k], EY(i0), i1 ? EY(i1) : 0, sy);
+      if (EZ(i0) || (i1 && EZ(i1))) sz = dot2_acc(Gr[k], EZ(i0), i1 ? EZ(i1) : 0, sz);
+    }
+    m0 = __builtin_fmaf(c.inv_scale_g, a, c.p0);
+    mx = c.inv_scale_g * sx;
+    my = c.inv_scale_g * sy;
+    mz = c.inv_scale_g * sz;
+  } else {
+    float G[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) G[i] = g_of<S>(Gr, i);
+    lean_moments(c, G, m0, mx, my, mz);
+  }
 }
 
 // Inputs of the collision at a node.

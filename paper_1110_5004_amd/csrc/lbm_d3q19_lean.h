@@ -355,7 +355,8 @@ __device__ __forceinline__ float lean_collide(const CaseDev& c, const LeanNode& 
     const float fm = __builtin_fmaf(omf, f_of<S>(Fr, i + 1), wf * (P - R));
     const uint32_t ef = enc_pair<S>(fp, fm);
     outf[j] = ef;
-    fsum += lo16<S>(ef) + hi16<S>(ef);
+    if constexpr (S == ST_FP16) fsum = dot2_acc(ef, 1.0f, 1.0f, fsum);
+    else fsum += lo16<S>(ef) + hi16<S>(ef);
     // g planes 2j-2, 2j-1
     outg[j - 1] = enc_pair_sr<S>(gprev, gp, sr_bits(nkey, 2 * j - 2), sr_bits(nkey, 2 * j - 1));
     gprev = gm;  // plane 2j goes with the next pair

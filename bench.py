@@ -131,19 +131,24 @@ def traffic_for(key, dim, seconds_per_launch):
     return round(e["bytes_per_launch"] / seconds_per_launch / 1e9, 1), e["bytes_per_launch"]
 
 
-def kernel_name(hip, dim, variant, remove_fa, storage):
-    """The step kernel a launch variant runs (the same choice the launcher
-    makes: the fused D3Q19 step drops the lap mu stage when the Eq. 5
-    coefficient is zero, i.e. for the original model)."""
+def kernel_name(hip, dim, variant, params, storage):
+    """The step kernel a launch variant runs, chosen as the launcher chooses:
+    the D3Q19 fused step drops the lap mu stage when the Eq. 5 coefficient
+    (d rho / d phi theta_M, kept only by remove_fa = 1) is zero."""
     if dim == 2:
         return "k_tile (fused D2Q9 step)"
     if hip.variants(hip.D3Q19)[variant][2] < 16:
         return "k3_pull + k3_fields_t + k3_collide"
+    rf = params["remove_fa"]
+    coef_zero = rf != 1 or params["theta_m"] == 0.0 or params["rho_l"] == params["rho_g"]
     if storage != "fp32":
-        if remove_fa == 2:
+        if rf == 2:
             return "k3_pull + k3_fields_t + k3_collide (correction from data, 16-bit)"
-        return "k3_march (fused D3Q19 step, 16-bit storage)"
-    if remove_fa == 0:
+        return ("k3_march (fused D3Q19 step, 16-bit storage"
+                + (", no lap mu stage)" if coef_zero else ")"))
+    if rf == 2:
+        return "k3_slab (fused D3Q19 step, correction from data)"
+    if coef_zero:
         return "k3_slab2 (fused D3Q19 step without the Eq. 5 term)"
     return "k3_slab (fused D3Q19 step)"
 
@@ -164,7 +169,7 @@ def leg(torch, W, hip, workload, storage, remove_fa, steps, warmup, variant=-1):
     return dict(mlups=round(case.n * steps / t / 1e6, 1), ms_per_step=round(1e3 * step_s, 5),
                 achieved_gbs=round(ach, 1), frac=round(ach / HBM_PEAK_GBS, 4),
                 bytes_per_lu=bpl, nodes=case.n, variant=variant,
-                kernel=kernel_name(hip, dim, variant, remove_fa, storage),
+                kernel=kernel_name(hip, dim, variant, case.params, storage),
                 mass_drift_rel=d["mass_drift_rel"], nonfinite=int(d["nonfinite"]),
                 umax=d["umax"])
 
@@ -296,6 +301,28 @@ def pull_copy_ceiling(torch, hip, lattice, storage, dims, reps=50):
     return t
 
 
+def copy_ceiling_gbs(torch, hip, nbytes=1 << 31, reps=20):
+    """GB/s (read + written) of lbm_copy_bw on two HBM-resident buffers of
+    nbytes: the plain-copy ceiling of the device (16-byte non-temporal loads
+    and stores, four per thread and round)."""
+    n = nbytes // 4
+    a = torch.zeros(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        hip.copy_bw(a, b)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        hip.copy_bw(a, b)
+    e1.record()
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) / 1e3 / reps
+    del a, b
+    return 2.0 * nbytes / t / 1e9
+
+
 def _cpu_model():
     try:
         with open("/proc/cpuinfo") as f:
@@ -367,6 +394,7 @@ def main():
             "splash1024x512": (1024, 512, 1)}[a.workload]
     lattice = hip.D3Q19 if dim == 3 else hip.D2Q9
     pc_s = pull_copy_ceiling(torch, hip, lattice, a.storage, dims[:dim])
+    copy_gbs = copy_ceiling_gbs(torch, hip)
     out = {
         "metric": METRIC,
         "value": main_leg["mlups"],
@@ -389,7 +417,10 @@ def main():
                      "variant": main_leg["variant"],
                      # the same reads and writes without arithmetic (lbm_pull_copy_bw)
                      "pull_copy_us": round(pc_s * 1e6, 2),
-                     "frac_of_pull_copy": round(pc_s / step_s, 4)},
+                     "frac_of_pull_copy": round(pc_s / step_s, 4),
+                     # a plain 2 GiB copy (lbm_copy_bw): the device's HBM copy ceiling
+                     "copy_gbs": round(copy_gbs, 1),
+                     "frac_of_copy": round(main_leg["achieved_gbs"] / copy_gbs, 4)},
         "check": {"mass_drift_rel": main_leg["mass_drift_rel"],
                   "nonfinite": main_leg["nonfinite"], "umax": main_leg["umax"]},
     }

@@ -96,21 +96,37 @@ hipError_t encode16(int storage, const float* in, uint16_t* out, long long n,
 // Coalesced 16-byte copy; tail handled element-wise.
 __global__ void __launch_bounds__(256)
 k_copy(const float* __restrict__ in, float* __restrict__ out, long long n) {
+  // four 16-byte words per thread and round, non-temporal loads and stores:
+  // the fastest plain copy measured here (5.9 TB/s HBM-resident against 4.9
+  // for one word per thread and cached accesses)
+  typedef float v4f __attribute__((ext_vector_type(4)));
   const long long n4 = n / 4;
-  const float4* i4 = reinterpret_cast<const float4*>(in);
-  float4* o4 = reinterpret_cast<float4*>(out);
-  const long long step = (long long)gridDim.x * blockDim.x;
-  for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < n4; k += step)
-    o4[k] = i4[k];
+  const v4f* i4 = reinterpret_cast<const v4f*>(in);
+  v4f* o4 = reinterpret_cast<v4f*>(out);
+  constexpr int U = 4;
+  const long long step = (long long)gridDim.x * blockDim.x * U;
+  for (long long k = blockIdx.x * (long long)blockDim.x * U + threadIdx.x; k < n4; k += step) {
+    v4f v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const long long j = k + (long long)u * blockDim.x;
+      if (j < n4) v[u] = __builtin_nontemporal_load(&i4[j]);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const long long j = k + (long long)u * blockDim.x;
+      if (j < n4) __builtin_nontemporal_store(v[u], &o4[j]);
+    }
+  }
   for (long long k = n4 * 4 + blockIdx.x * (long long)blockDim.x + threadIdx.x; k < n;
-       k += step)
+       k += (long long)gridDim.x * blockDim.x)
     out[k] = in[k];
 }
 
 hipError_t copy_bw(const float* in, float* out, long long n, hipStream_t stream) {
   if (n <= 0) return hipSuccess;
-  long long blocks = (n / 4 + 255) / 256;
-  const int grid = (int)(blocks < 8192 ? (blocks > 0 ? blocks : 1) : 8192);
+  long long blocks = (n / 16 + 255) / 256;
+  const int grid = (int)(blocks < 32768 ? (blocks > 0 ? blocks : 1) : 32768);
   hipLaunchKernelGGL(k_copy, dim3(grid), dim3(256), 0, stream, in, out, n);
   return hipGetLastError();
 }

@@ -393,3 +393,14 @@ def test_pull_copy_moves_words(torch, hip, lattice, dims, storage):
     for off, w in tail:
         want[off:off + w * n] = src_h[off:off + w * n]
     assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("n", [1, 15, 16, 4096 * 3 + 7, (1 << 22) + 5])
+def test_copy_bw_moves_words(torch, hip, n):
+    """The copy-ceiling kernel copies every word (ragged sizes: the 16-byte
+    rounds and the float tail)."""
+    x = torch.randn(n, device="cuda")
+    y = torch.full((n,), float("nan"), device="cuda")
+    hip.copy_bw(x, y)
+    torch.cuda.synchronize()
+    assert torch.equal(x, y)

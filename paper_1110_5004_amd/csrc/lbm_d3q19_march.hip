@@ -257,6 +257,15 @@ struct GLoads {
 // first population of each packed pair, odd lane: the second; the odd lane's
 // offset adds the uniform difference between the two pulls).  Seam / wall:
 // one word per population, packed.
+// Inner sites load a pair of planes as lane-pair words only where both pulls
+// keep the 4-byte alignment of the pair's even node (no x shift: e_x = 0);
+// pulls shifted along x would make those words straddle 4-byte boundaries,
+// and the unaligned dword costs more than the two 2-byte loads it saves.
+__device__ __forceinline__ constexpr bool f_paired(int j) { return EX(PI(j)) == 0; }
+__device__ __forceinline__ constexpr bool g_paired(int q) {
+  return EX(2 * q) == 0 && (2 * q + 1 >= Q || EX(2 * q + 1) == 0);
+}
+
 template <int S, int MODE>
 __device__ __forceinline__ void issue_f(const CaseDev& c, Rsrc src, const PlaneOfs& po, int qx,
                                         int qy, int k, uint32_t odd, FLoads& L) {
@@ -267,7 +276,8 @@ __device__ __forceinline__ void issue_f(const CaseDev& c, Rsrc src, const PlaneO
     for (int j = 1; j <= 9; ++j) {
       const unsigned a = inner_soff<false>(c, po, k, PI(j));
       const unsigned b = inner_soff<false>(c, po, k, PI(j) + 1);
-      L.w[j] = pair_load(src, base, a, b, 0u - odd);
+      if (f_paired(j)) L.w[j] = pair_load(src, base, a, b, 0u - odd);
+      else L.w[j] = pack16(bload16(src, s.self, a), bload16(src, s.self, b));
     }
     L.f0 = bload32f(src, 2u * s.self, 2u * po.z2 * (unsigned)k);
   } else {
@@ -290,7 +300,8 @@ __device__ __forceinline__ void issue_g(const CaseDev& c, Rsrc src, const PlaneO
     for (int q = 0; q < 10; ++q) {
       const int i = 2 * q, i2 = 2 * q + 1 < Q ? 2 * q + 1 : 2 * q;
       const unsigned a = inner_soff<true>(c, po, k, i), b = inner_soff<true>(c, po, k, i2);
-      L.w[q] = pair_load(src, base, a, b, 0u - odd);
+      if (g_paired(q)) L.w[q] = pair_load(src, base, a, b, 0u - odd);
+      else L.w[q] = pack16(bload16(src, s.self, a), i2 != i ? bload16(src, s.self, b) : (uint16_t)0);
     }
   } else {
     uint16_t h[Q + 1];
@@ -400,7 +411,7 @@ __device__ __forceinline__ void march_loop(const CaseDev& c, MarchLds<TX, TY, RF
           uint32_t w[10];
 #pragma unroll
           for (int j = 1; j <= 9; ++j)
-            w[j] = MODE == AD_INNER ? pair_xchg(lf[q].w[j], psel) : lf[q].w[j];
+            w[j] = MODE == AD_INNER && f_paired(j) ? pair_xchg(lf[q].w[j], psel) : lf[q].w[j];
           int px, py;
           phi_pos(r, px, py);
           php[b + px + PX * py] = lean_phi_packed<S>(c, lf[q].f0, w);
@@ -454,7 +465,8 @@ __device__ __forceinline__ void march_loop(const CaseDev& c, MarchLds<TX, TY, RF
             uint32_t gwd[10];
 #pragma unroll
             for (int kq = 0; kq < 10; ++kq)
-              gwd[kq] = MODE == AD_INNER ? pair_xchg(lg[q].w[kq], psel) : lg[q].w[kq];
+              gwd[kq] = MODE == AD_INNER && g_paired(kq) ? pair_xchg(lg[q].w[kq], psel)
+                                                         : lg[q].w[kq];
             if (q == 0) {
               const int gs = (k + 2) & 1;
 #pragma unroll

@@ -404,3 +404,59 @@ def test_copy_bw_moves_words(torch, hip, n):
     hip.copy_bw(x, y)
     torch.cuda.synchronize()
     assert torch.equal(x, y)
+
+
+@pytest.mark.parametrize("lattice,storage,variant", [("d2q9", "fp16", None), ("d2q9", "bf16", None),
+                                                     ("d3q19", "fp16", 12), ("d3q19", "fp16", 1),
+                                                     ("d3q19", "bf16", 12)])
+def test_checkpoint_resume_bitwise_16bit(torch, hip, lattice, storage, variant):
+    """16-bit storage rounds g stochastically with bits keyed by the time
+    step, so a resumed run must restore the step counter: 120 steps = 61 +
+    save + load (lbm_set_state, lbm_set_step) + 59, bit for bit, on a handle
+    whose copy parity differs from the saved one's."""
+    if lattice == "d2q9":
+        case = W.stationary_droplet(seed=9, n=64, radius=12.0, remove_fa=1)
+    else:
+        prm = W.base_params(W.D3Q19, 24, 20, 16, (0, 0, 1), sigma=0.01, gravity=1e-5,
+                            remove_fa=1)
+        case = W.Case(prm, *W.droplet_fields(prm, (11.3, 9.6, 7.8), 6.0, impact_u=0.02))
+
+    def sim():
+        s = hip.Simulation([case], storage=storage)
+        if variant is not None:
+            s.set_launch(variant, 0, 16)
+        return s
+    a = sim()
+    a.step(120)
+    b = sim()
+    b.step(61)
+    st = b.get_state()
+    c = sim()
+    c.set_state(st, step=61)
+    c.step(59)
+    assert c.time == 120
+    assert np.array_equal(a.get_state(), c.get_state())
+    for s_ in (a, b, c):
+        s_.close()
+
+
+@pytest.mark.parametrize("lattice", ["d2q9", "d3q19"])
+def test_prepare_captures_without_advancing(torch, hip, lattice):
+    """lbm_prepare captures the step graph and changes neither the state nor
+    the time level; the steps that replay it give the bits of a handle that
+    captured on its first step."""
+    if lattice == "d2q9":
+        case = W.stationary_droplet(seed=4, n=64, radius=12.0, remove_fa=1)
+    else:
+        prm = W.base_params(W.D3Q19, 24, 20, 16, (0, 0, 1), sigma=0.01, remove_fa=1)
+        case = W.Case(prm, *W.droplet_fields(prm, (11.3, 9.6, 7.8), 6.0, impact_u=0.02))
+    a = hip.Simulation([case], storage="fp16")
+    s0 = a.get_state()
+    a.prepare()
+    assert a.time == 0 and np.array_equal(a.get_state(), s0)
+    a.step(48)
+    b = hip.Simulation([case], storage="fp16")
+    b.step(48)
+    assert np.array_equal(a.get_state(), b.get_state())
+    a.close()
+    b.close()

@@ -133,7 +133,8 @@ hipError_t copy_bw(const float* in, float* out, long long n, hipStream_t stream)
 
 // Pull-copy: the data movement of one step without its arithmetic.  Every
 // stored word of node idx is read from the node the step pulls it from
-// (x - e_i, or idx itself where that leaves the grid) and written to idx.
+// (x - e_i, or idx itself where that leaves the grid) and written to idx,
+// with the non-temporal stores of the step kernels.
 template <int LAT, int S>
 __global__ void __launch_bounds__(256)
 k_pull_copy(CaseDev c, const char* __restrict__ src, char* __restrict__ dst) {
@@ -156,17 +157,17 @@ k_pull_copy(CaseDev c, const char* __restrict__ src, char* __restrict__ dst) {
                     z - ez >= 0 && z - ez < c.nz;
     const unsigned j = in ? (unsigned)(idx - ex - c.nx * (ey + c.ny * ez)) : (unsigned)idx;
     if (S == ST_FP32 || i == 0)
-      gstore<uint32_t>(dst, P::fofs(c, i, idx), gload<uint32_t>(src, P::fofs(c, i, j)));
+      gstore_nt<uint32_t>(dst, P::fofs(c, i, idx), gload<uint32_t>(src, P::fofs(c, i, j)));
     else
-      gstore<uint16_t>(dst, P::fofs(c, i, idx), gload<uint16_t>(src, P::fofs(c, i, j)));
+      gstore_nt<uint16_t>(dst, P::fofs(c, i, idx), gload<uint16_t>(src, P::fofs(c, i, j)));
     if (S == ST_FP32)
-      gstore<uint32_t>(dst, P::gofs(c, i, idx), gload<uint32_t>(src, P::gofs(c, i, j)));
+      gstore_nt<uint32_t>(dst, P::gofs(c, i, idx), gload<uint32_t>(src, P::gofs(c, i, j)));
     else
-      gstore<uint16_t>(dst, P::gofs(c, i, idx), gload<uint16_t>(src, P::gofs(c, i, j)));
+      gstore_nt<uint16_t>(dst, P::gofs(c, i, idx), gload<uint16_t>(src, P::gofs(c, i, j)));
   }
   if (S == ST_FP32) {
     const unsigned lo = (unsigned)(2 * Q) * 4u * c.stride;
-    gstore<uint16_t>(dst, lo + 2u * idx, gload<uint16_t>(src, lo + 2u * idx));
+    gstore_nt<uint16_t>(dst, lo + 2u * idx, gload<uint16_t>(src, lo + 2u * idx));
   }
 }
 

@@ -757,7 +757,7 @@ __device__ __forceinline__ void tile_bcd(TileLds<TX, TY, RF>& L, const CaseDev& 
       two_sum(phh, -fsum, h0, e0);
       op.put_f0(idx, h0, e0 + phl);
       // the copy carries this step's phi, the next step's phi^(n-1)
-      if constexpr (RF == 2) gstore<float>(dst, c.phiv + 4u * idx, ph);
+      if constexpr (RF == 2) gstore_nt<float>(dst, c.phiv + 4u * idx, ph);
     }
   }
   __syncthreads();
@@ -875,7 +875,7 @@ k_init(CaseDev c, int parity, const double* __restrict__ phi0, const double* __r
   two_sum(nh[0], -fsum, h0, e0);
   P::put_f0(c, dst, idx, h0, e0 + nl[0]);
   // correction from data: phi^(n-1) of the first step is phi0
-  if (c.phiv) gstore<float>(dst, c.phiv + 4u * idx, ph);
+  if (c.phiv) gstore_nt<float>(dst, c.phiv + 4u * idx, ph);
 }
 
 }  // namespace d2q9

@@ -40,6 +40,11 @@ struct Fields3 {
   float* dd;  // correction from data: the rate D of -F_a = D u
 };
 
+// Store of a field plane value that the next kernel of the step reads.
+__device__ __forceinline__ void plane_put(float* a, unsigned idx, float v) {
+  gstore_nt<float>(reinterpret_cast<char*>(a), 4u * idx, v);
+}
+
 // phi = sum_i f_i of the pulled populations (Eq. 4a's zeroth moment), as a
 // float-float pair: f_0 (high and low part) plus the sum of the others.
 template <int S, class N>
@@ -100,12 +105,12 @@ __global__ void __launch_bounds__(256) k3_pull(CaseDev c, int parity, Fields3 fl
     pull_phi<S>(c, src, nd, hi, lo);
     pull_moments<S>(c, src, nd, m0, mx, my, mz);
   }
-  fl.phh[idx] = hi;
-  if constexpr (S == ST_FP32) fl.phl[idx] = lo;  // 16-bit: phi is one float
-  fl.m0[idx] = m0;
-  fl.m1x[idx] = mx;
-  fl.m1y[idx] = my;
-  fl.m1z[idx] = mz;
+  plane_put(fl.phh, idx, hi);
+  if constexpr (S == ST_FP32) plane_put(fl.phl, idx, lo);  // 16-bit: phi is one float
+  plane_put(fl.m0, idx, m0);
+  plane_put(fl.m1x, idx, mx);
+  plane_put(fl.m1y, idx, my);
+  plane_put(fl.m1z, idx, mz);
 }
 
 // Isotropic gradient 3 sum_i w_i e_i f_i of a node field, from differences
@@ -347,15 +352,15 @@ k3_fields_t(CaseDev c, Fields3 fl, int dump, int parity) {
       gather18<MX, MY>(L.qz, mc, qz);
       cc = __builtin_fmaf(ph - gload<float>(src, c.phiv + 4u * idx), c.drho,
                           lean_div(qx, qy, qz));
-      fl.dd[idx] = cc;
+      plane_put(fl.dd, idx, cc);
     }
     const LeanUP r = lean_recover(c, ph, mu, g[0], g[1], g[2], cc, m0, m1x, m1y, m1z);
     if (dump) fl.mu[idx] = mu;
-    fl.ux[idx] = r.ux;
-    fl.uy[idx] = r.uy;
-    fl.uz[idx] = r.uz;
-    fl.p[idx] = r.p;
-    fl.lmu[idx] = lmu;
+    plane_put(fl.ux, idx, r.ux);
+    plane_put(fl.uy, idx, r.uy);
+    plane_put(fl.uz, idx, r.uz);
+    plane_put(fl.p, idx, r.p);
+    plane_put(fl.lmu, idx, lmu);
     return;
   } else {
     const float h0 = L.ph[pc], l0 = L.pl[pc];
@@ -400,7 +405,7 @@ k3_fields_t(CaseDev c, Fields3 fl, int dump, int parity) {
         dv += w * e;
       }
       cc = (ph - gload<float>(src, c.phiv + 4u * idx)) * c.drho + dv;
-      fl.dd[idx] = cc;
+      plane_put(fl.dd, idx, cc);
     }
     const float iden = __builtin_amdgcn_rcpf(rho - 0.5f * cc);
     const float ux = (3.0f * m1x + 0.5f * fsx) * iden;
@@ -409,11 +414,11 @@ k3_fields_t(CaseDev c, Fields3 fl, int dump, int parity) {
     // mu for the field dump only: the collision forms mu and grad phi again from
     // the phi planes (phi_grad_mu), with these expressions in this order
     if (dump) fl.mu[idx] = mu;
-    fl.ux[idx] = ux;
-    fl.uy[idx] = uy;
-    fl.uz[idx] = uz;
-    fl.p[idx] = m0 + (1.0f / 6.0f) * c.drho * (ux * g[0] + uy * g[1] + uz * g[2]);
-    fl.lmu[idx] = lmu;
+    plane_put(fl.ux, idx, ux);
+    plane_put(fl.uy, idx, uy);
+    plane_put(fl.uz, idx, uz);
+    plane_put(fl.p, idx, m0 + (1.0f / 6.0f) * c.drho * (ux * g[0] + uy * g[1] + uz * g[2]));
+    plane_put(fl.lmu, idx, lmu);
   }
 }
 
@@ -585,16 +590,17 @@ template <int S>
 __device__ __forceinline__ void store_lean(const CaseDev& c, char* dst, unsigned idx, float f0,
                                            const uint32_t* og, const uint32_t* of) {
   using P = Pops<S, Q>;
-  gstore<float>(dst, 4u * idx, f0);
+  gstore_nt<float>(dst, 4u * idx, f0);
 #pragma unroll
   for (int j = 1; j <= 9; ++j) {
-    gstore<uint16_t>(dst, P::fofs(c, PI(j), idx), (uint16_t)(of[j] & 0xffffu));
-    gstore<uint16_t>(dst, P::fofs(c, PI(j) + 1, idx), (uint16_t)(of[j] >> 16));
+    gstore_nt<uint16_t>(dst, P::fofs(c, PI(j), idx), (uint16_t)(of[j] & 0xffffu));
+    gstore_nt<uint16_t>(dst, P::fofs(c, PI(j) + 1, idx), (uint16_t)(of[j] >> 16));
   }
 #pragma unroll
   for (int k = 0; k < 10; ++k) {
-    gstore<uint16_t>(dst, P::gofs(c, 2 * k, idx), (uint16_t)(og[k] & 0xffffu));
-    if (2 * k + 1 < Q) gstore<uint16_t>(dst, P::gofs(c, 2 * k + 1, idx), (uint16_t)(og[k] >> 16));
+    gstore_nt<uint16_t>(dst, P::gofs(c, 2 * k, idx), (uint16_t)(og[k] & 0xffffu));
+    if (2 * k + 1 < Q)
+      gstore_nt<uint16_t>(dst, P::gofs(c, 2 * k + 1, idx), (uint16_t)(og[k] >> 16));
   }
 }
 
@@ -640,7 +646,7 @@ __global__ void __launch_bounds__(256) k3_collide(CaseDev c, int parity, Fields3
     const uint32_t nkey = sr_node_key(sr_step_key(sr_clock(c, parity)), idx);
     const float f0 = lean_collide<S>(c, n, gp[0], gp[1], gp[2], Gr, Fr, og, of, nkey);
     store_lean<S>(c, dst, idx, f0, og, of);
-    if (c.phiv) gstore<float>(dst, c.phiv + 4u * idx, n.ph);
+    if (c.phiv) gstore_nt<float>(dst, c.phiv + 4u * idx, n.ph);
     return;
   }
   const OutPtrs<S, Q> op(c, dst);
@@ -660,7 +666,7 @@ __global__ void __launch_bounds__(256) k3_collide(CaseDev c, int parity, Fields3
   n.gpz = gp[2];
   collide_node<S>(c, op, idx, fv, gv, n);
   // correction from data: the copy carries this step's phi
-  if (c.phiv) gstore<float>(dst, c.phiv + 4u * idx, n.phh + n.phl);
+  if (c.phiv) gstore_nt<float>(dst, c.phiv + 4u * idx, n.phh + n.phl);
 }
 
 // ---- fused step: one x-y tile of the grid marching up a chunk of z planes
@@ -1007,7 +1013,7 @@ __global__ void __launch_bounds__(TX * TY) k3_slab(CaseDev c, int parity, int zs
       cur.gpz = az;
       collide_node<S>(c, op, nd.idx, fa, gv, cur);
       // correction from data: the copy carries this step's phi
-      if constexpr (RF2) gstore<float>(op.base, c.phiv + 4u * nd.idx, cur.phh + cur.phl);
+      if constexpr (RF2) gstore_nt<float>(op.base, c.phiv + 4u * nd.idx, cur.phh + cur.phl);
     }
     cur = nxt;
 #pragma unroll
@@ -1283,7 +1289,7 @@ k3_init(CaseDev c, int parity, const double* __restrict__ phi0, const double* __
   two_sum(h0, -fsum, hh, ee);
   P::put_f0(c, dst, idx, hh, ee + l0);
   // correction from data: phi^(n-1) of the first step is phi0
-  if (c.phiv) gstore<float>(dst, c.phiv + 4u * idx, ph);
+  if (c.phiv) gstore_nt<float>(dst, c.phiv + 4u * idx, ph);
 }
 
 }  // namespace d3q19

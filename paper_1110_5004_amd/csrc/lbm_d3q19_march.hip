@@ -109,11 +109,16 @@ __device__ __forceinline__ uint32_t bload32(Rsrc r, unsigned voff, unsigned soff
 __device__ __forceinline__ float bload32f(Rsrc r, unsigned voff, unsigned soff) {
   return __uint_as_float(bload32(r, voff, soff));
 }
+// Stores carry the non-temporal cache policy (bit 1 of the buffer
+// instruction's cache-policy operand): a stored population is not read again
+// until the next step, and streaming it past the caches leaves them to the
+// halo lines the march re-reads.
+constexpr int kStoreNT = 2;
 __device__ __forceinline__ void bstore16(Rsrc r, unsigned voff, unsigned soff, uint16_t v) {
-  __builtin_amdgcn_raw_buffer_store_b16(v, r, (int)voff, (int)soff, 0);
+  __builtin_amdgcn_raw_buffer_store_b16(v, r, (int)voff, (int)soff, kStoreNT);
 }
 __device__ __forceinline__ void bstore32(Rsrc r, unsigned voff, unsigned soff, uint32_t v) {
-  __builtin_amdgcn_raw_buffer_store_b32(v, r, (int)voff, (int)soff, 0);
+  __builtin_amdgcn_raw_buffer_store_b32(v, r, (int)voff, (int)soff, kStoreNT);
 }
 __device__ __forceinline__ void bstore32f(Rsrc r, unsigned voff, unsigned soff, float v) {
   bstore32(r, voff, soff, __float_as_uint(v));

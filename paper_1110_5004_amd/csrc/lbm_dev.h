@@ -188,6 +188,14 @@ template <class T>
 __device__ __forceinline__ void gstore(char* base, unsigned byte_off, T v) {
   *(LBM_GLOBAL T*)((LBM_GLOBAL char*)base + byte_off) = v;
 }
+// Store of a population (or of a field plane that the next kernel reads once):
+// a word written once per step and read again only after the whole grid has
+// been swept.  The non-temporal hint streams it past the caches, so it does
+// not displace the lines the kernel re-reads (halo positions, stencil planes).
+template <class T>
+__device__ __forceinline__ void gstore_nt(char* base, unsigned byte_off, T v) {
+  __builtin_nontemporal_store(v, (LBM_GLOBAL T*)((LBM_GLOBAL char*)base + byte_off));
+}
 
 // Plane layout of one copy (Q velocities):
 //   FP32:      f_0..f_{Q-1}, g_0..g_{Q-1} as float planes, then the BF16 low
@@ -246,11 +254,11 @@ struct Pops {
   static __device__ __forceinline__ float put_f(const CaseDev& c, char* base, int i, unsigned j,
                                                 float v) {
     if constexpr (S == ST_FP32) {
-      gstore<float>(base, fofs(c, i, j), v);
+      gstore_nt<float>(base, fofs(c, i, j), v);
       return v;
     } else {
       const uint16_t h = enc16<S>(v * c.scale_f);
-      gstore<uint16_t>(base, fofs(c, i, j), h);
+      gstore_nt<uint16_t>(base, fofs(c, i, j), h);
       return Pops<S, Q>::dec_f(c, h);
     }
   }
@@ -260,19 +268,19 @@ struct Pops {
     if constexpr (S == ST_FP32) {
       float h, l;
       two_sum(hi, lo, h, l);
-      gstore<float>(base, 4u * j, h);
-      gstore<uint16_t>(base, (unsigned)(2 * Q) * 4u * c.stride + 2u * j, enc_bf16(l));
+      gstore_nt<float>(base, 4u * j, h);
+      gstore_nt<uint16_t>(base, (unsigned)(2 * Q) * 4u * c.stride + 2u * j, enc_bf16(l));
     } else {
-      gstore<float>(base, 4u * j, hi + lo);
+      gstore_nt<float>(base, 4u * j, hi + lo);
     }
   }
   static __device__ __forceinline__ void put_g(const CaseDev& c, char* base, int i, unsigned j,
                                                float v, float wi) {
     if constexpr (S == ST_FP32) {
       (void)wi;
-      gstore<float>(base, gofs(c, i, j), v);
+      gstore_nt<float>(base, gofs(c, i, j), v);
     } else {
-      gstore<uint16_t>(base, gofs(c, i, j), enc16<S>((v - wi * c.p0) * c.scale_g));
+      gstore_nt<uint16_t>(base, gofs(c, i, j), enc16<S>((v - wi * c.p0) * c.scale_g));
     }
   }
 };
@@ -297,28 +305,28 @@ struct OutPtrs {
   // store f_i (i > 0) at node idx; returns what was stored (decoded)
   __device__ __forceinline__ float put_f(const CaseDev& c, int i, unsigned idx, float v) const {
     if constexpr (S == ST_FP32) {
-      gstore<float>(f[i], 4u * idx, v);
+      gstore_nt<float>(f[i], 4u * idx, v);
       return v;
     } else {
       const uint16_t h = enc16<S>(v * c.scale_f);
-      gstore<uint16_t>(f[i], 2u * idx, h);
+      gstore_nt<uint16_t>(f[i], 2u * idx, h);
       return Pops<S, Q>::dec_f(c, h);
     }
   }
   // store g_i at node idx; 16-bit: rounded stochastically with the bits r
   __device__ __forceinline__ void put_g(const CaseDev& c, int i, unsigned idx, float v,
                                         float wi, uint32_t r) const {
-    if constexpr (S == ST_FP32) gstore<float>(g[i], 4u * idx, v);
-    else gstore<uint16_t>(g[i], 2u * idx, enc16_sr<S>((v - wi * c.p0) * c.scale_g, r));
+    if constexpr (S == ST_FP32) gstore_nt<float>(g[i], 4u * idx, v);
+    else gstore_nt<uint16_t>(g[i], 2u * idx, enc16_sr<S>((v - wi * c.p0) * c.scale_g, r));
   }
   __device__ __forceinline__ void put_f0(unsigned idx, float hi, float lo) const {
     if constexpr (S == ST_FP32) {
       float h, l;
       two_sum(hi, lo, h, l);
-      gstore<float>(f[0], 4u * idx, h);
-      gstore<uint16_t>(f0lo, 2u * idx, enc_bf16(l));
+      gstore_nt<float>(f[0], 4u * idx, h);
+      gstore_nt<uint16_t>(f0lo, 2u * idx, enc_bf16(l));
     } else {
-      gstore<float>(f[0], 4u * idx, hi + lo);
+      gstore_nt<float>(f[0], 4u * idx, hi + lo);
     }
   }
 };

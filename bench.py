@@ -137,9 +137,12 @@ def kernel_name(hip, dim, variant, params, storage):
     (d rho / d phi theta_M, kept only by remove_fa = 1) is zero."""
     if dim == 2:
         return "k_tile (fused D2Q9 step)"
-    if hip.variants(hip.D3Q19)[variant][2] < 16:
-        return "k3_pull + k3_fields_t + k3_collide"
+    form = hip.variants(hip.D3Q19)[variant][4]
     rf = params["remove_fa"]
+    if form == hip.FORM_TWO and storage != "fp32" and rf != 2:
+        return "k3_pull + k3_fcm (two-kernel D3Q19 step, 16-bit storage)"
+    if form != hip.FORM_FUSED:
+        return "k3_pull + k3_fields_t + k3_collide"
     coef_zero = rf != 1 or params["theta_m"] == 0.0 or params["rho_l"] == params["rho_g"]
     if storage != "fp32":
         if rf == 2:

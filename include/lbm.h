@@ -311,14 +311,23 @@ int lbm_set_launch(lbm_handle* h, int32_t variant, int32_t grid_blocks, int32_t 
 int lbm_get_launch(const lbm_handle* h, int32_t* variant, int32_t* grid_blocks,
                    int32_t* graph_steps);
 /* Number of compiled tile variants for a lattice, and the tile (nodes per
- * axis) and workgroup size of one.  D3Q19: variants whose tz is below 16 are
- * the three-kernel step, named by the tile of its fields kernel; those with tz
- * of 16 or more are the fused step, one tx x ty tile of the x-y plane marching
- * up a chunk of tz planes.  Every variant of a lattice computes the same bits,
- * in every model and storage layout. */
+ * axis) and workgroup size of one.  For D3Q19 the tile belongs to the step
+ * form that lbm_variant_form reports.  Every variant of a lattice computes
+ * the same bits, in every model and storage layout. */
 int lbm_variant_count(int32_t lattice, int32_t* count);
 int lbm_variant_info(int32_t lattice, int32_t variant, int32_t* tx, int32_t* ty, int32_t* tz,
                      int32_t* threads);
+/* The D3Q19 step form of a variant (D2Q9: always 0):
+ *   0  three kernels: pull, the fields on tx x ty x tz tiles, collision;
+ *   1  fused: one kernel, a tx x ty tile of the x-y plane marching up a chunk
+ *      of tz planes with the fields in LDS;
+ *   2  two kernels (16-bit storage): the pull, then a tx x ty tile marching up
+ *      a chunk of tz planes that forms the fields and collides.
+ * Form 1 with 16-bit storage on a grid of odd width or with the correction
+ * from data, form 2 with FP32 storage or the correction from data, run the
+ * three-kernel step of variant 1.  LBM_ERR_ARG for a NULL form, a bad lattice
+ * or a variant out of range. */
+int lbm_variant_form(int32_t lattice, int32_t variant, int32_t* form);
 
 void lbm_free(lbm_handle* h);
 const char* lbm_last_error(void);

@@ -6,7 +6,8 @@ interfacial force F_a, as hand-written HIP kernels behind the C ABI of
 include/lbm.h.  This package only marshals arguments (binding.py) and builds
 the library (build.py).
 """
-from .binding import (BF16, D2Q9, D3Q19, FP16, FP32, PERIODIC, WALL, LbmError, Simulation,
+from .binding import (BF16, D2Q9, D3Q19, FORM_FUSED, FORM_THREE, FORM_TWO, FP16, FP32, PERIODIC,
+                      WALL, LbmError, Simulation,
                       beta_kappa, beta_kappa_sym, copy_bw, declared_functions, encode16,
                       encode16_stochastic,
                       field_diagnostics, field_diagnostics_noalloc, lib, pull_copy_bw,
@@ -14,4 +15,5 @@ from .binding import (BF16, D2Q9, D3Q19, FP16, FP32, PERIODIC, WALL, LbmError, S
 
 __all__ = ["Simulation", "LbmError", "beta_kappa", "beta_kappa_sym", "lib", "stream_words", "encode16", "encode16_stochastic",
            "copy_bw", "field_diagnostics", "field_diagnostics_noalloc", "pull_copy_bw", "pull_copy_bytes", "variants", "declared_functions",
-           "D2Q9", "D3Q19", "PERIODIC", "WALL", "FP32", "FP16", "BF16"]
+           "D2Q9", "D3Q19", "PERIODIC", "WALL", "FP32", "FP16", "BF16",
+           "FORM_THREE", "FORM_FUSED", "FORM_TWO"]

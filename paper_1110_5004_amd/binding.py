@@ -99,6 +99,7 @@ def lib():
     L.lbm_get_launch.argtypes = [_vp, i32p, i32p, i32p]
     L.lbm_variant_count.argtypes = [C.c_int32, i32p]
     L.lbm_variant_info.argtypes = [C.c_int32, C.c_int32, i32p, i32p, i32p, i32p]
+    L.lbm_variant_form.argtypes = [C.c_int32, C.c_int32, i32p]
     L.lbm_free.argtypes = [_vp]
     L.lbm_free.restype = None
     L.lbm_stream_words.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_int32, i32p, _vp, _vp,
@@ -343,16 +344,21 @@ class Simulation:
         return v.value, g.value, s.value
 
 
+FORM_THREE, FORM_FUSED, FORM_TWO = 0, 1, 2
+
+
 def variants(lattice=D2Q9):
-    """[(tx, ty, tz, threads)] of the compiled tile shapes."""
+    """[(tx, ty, tz, threads, form)] of the compiled tile shapes (form: the
+    D3Q19 step form, FORM_THREE / FORM_FUSED / FORM_TWO; 0 for D2Q9)."""
     n = C.c_int32()
     _check(lib().lbm_variant_count(lattice, C.byref(n)))
     out = []
     for v in range(n.value):
-        tx, ty, tz, nt = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+        tx, ty, tz, nt, fm = (C.c_int32() for _ in range(5))
         _check(lib().lbm_variant_info(lattice, v, C.byref(tx), C.byref(ty), C.byref(tz),
                                       C.byref(nt)))
-        out.append((tx.value, ty.value, tz.value, nt.value))
+        _check(lib().lbm_variant_form(lattice, v, C.byref(fm)))
+        out.append((tx.value, ty.value, tz.value, nt.value, fm.value))
     return out
 
 

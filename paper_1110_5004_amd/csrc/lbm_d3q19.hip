@@ -12,7 +12,9 @@
 //                phi, lap mu, u and p (with -F_a in the corrected model)
 //   k3_collide   grad phi and mu again from the phi planes, grad p ->
 //                grad psi, BGK collision of f and gbar, store
-// Both compute every node to the same bits.  Stencil neighbours go through
+// or, with 16-bit storage, two: k3_pull, then k3_fcm, which marches x-y
+// tiles up z chunks doing the work of k3_fields_t and k3_collide with the
+// fields in LDS rings.  All forms compute every node to the same bits.  Stencil neighbours go through
 // the periodic / mirror mapping, so positions beyond a wall read their mirror
 // node.
 #include "lbm_d3q19_addr.h"
@@ -669,6 +671,262 @@ __global__ void __launch_bounds__(256) k3_collide(CaseDev c, int parity, Fields3
   if (c.phiv) gstore_nt<float>(dst, c.phiv + 4u * idx, n.phh + n.phl);
 }
 
+// ---- 2+3+4 as one march (16-bit storage, no correction from data): k3_fcm
+//
+// The step's second kernel after k3_pull.  A workgroup owns a TX x TY tile
+// of the x-y plane and the planes [za, zb) of one z chunk, and keeps rings of
+// planes in LDS:
+//   phi over the tile + 3, 4 planes (read from the plane k3_pull wrote)
+//   mu over the tile + 2, 3 planes
+//   p over the tile + 1, 3 planes
+// Iteration z stages phi(z + 3), forms mu(z + 2), forms grad phi, lap mu, u
+// and p at z + 1 from the moment planes of k3_pull (the own node keeps its
+// fields in registers for the next iteration), then collides plane z with
+// the own node's pulled populations.  No field plane goes back to HBM and the
+// stencils of the collision read LDS.  Every quantity is the same expression
+// in the same order as in k3_fields_t and k3_collide, so the step gives the
+// bits of the three-kernel step.
+//
+// Positions beyond a wall: phi is staged from the mirror node (periodic image
+// on periodic axes); in the x-y plane mu, u and p at such a position are
+// formed around the mirror position with the mirror node's moments, so they
+// equal the mirror node's values; along z the planes beyond a wall are not
+// formed and their reads go to the mirror plane.
+template <int TX, int TY>
+struct FcmLds {
+  static constexpr int PX = TX + 6, PY = TY + 6, NP = PX * PY;  // phi, tile + 3
+  static constexpr int MX = TX + 4, MY = TY + 4, NM = MX * MY;  // mu, tile + 2
+  static constexpr int UX = TX + 2, UY = TY + 2, NU = UX * UY;  // p, tile + 1
+  float ph[4][NP];
+  float mu[3][NM];
+  float p[3][NU];
+};
+
+template <int S, int TX, int TY>
+__global__ void __launch_bounds__(TX * TY) k3_fcm(CaseDev c, int parity, Fields3 fl, int zc) {
+  static_assert(S != ST_FP32, "the lean arithmetic of 16-bit storage");
+  using T = FcmLds<TX, TY>;
+  constexpr int NT = TX * TY, PX = T::PX, MX = T::MX, MY = T::MY, UX = T::UX, UY = T::UY;
+  constexpr int KP = (T::NP + NT - 1) / NT;      // phi positions per thread (at most)
+  constexpr int NRING = T::NU - NT;              // u, p positions outside the tile
+  constexpr int KU = 1 + (NRING + NT - 1) / NT;  // u, p positions per thread: own + ring
+  __shared__ T L;
+  // every workgroup reads the step counter; workgroup 0 advances it
+  const uint32_t skey = sr_step_key(sr_clock(c, parity));
+  // XCD-aware tile order: workgroup b runs on XCD b % 8 and takes the b / 8-th
+  // tile of that XCD's contiguous chunk (x fastest, then y, then the z chunk)
+  const int ntx = (c.nx + TX - 1) / TX, nty = (c.ny + TY - 1) / TY, ntz = (c.nz + zc - 1) / zc;
+  const int ntiles = ntx * nty * ntz;
+  const int chunk = (ntiles + 7) >> 3;
+  const int t = (blockIdx.x & 7) * chunk + (blockIdx.x >> 3);
+  if (blockIdx.x >= (unsigned)(8 * chunk) || t >= ntiles) return;
+  const int x0 = (t % ntx) * TX, y0 = ((t / ntx) % nty) * TY, za = (t / (ntx * nty)) * zc;
+  const int zb = min(za + zc, c.nz);
+  const int tid = threadIdx.x;
+  // no x-y position of the phi region needs the periodic or mirror mapping
+  const bool inner = x0 >= 3 && x0 + TX + 3 <= c.nx && y0 >= 3 && y0 + TY + 3 <= c.ny;
+  const int lx = tid % TX, ly = tid / TX;
+  const int gx = x0 + lx, gy = y0 + ly;
+  const bool own = gx < c.nx && gy < c.ny;
+  const unsigned pln = (unsigned)(c.nx * c.ny);
+  const char* src = parity ? c.state[1] : c.state[0];
+  char* dst = parity ? c.state[0] : c.state[1];
+  auto s4 = [](int k) { return (k + 8) & 3; };  // ring slots (k >= -6)
+  auto s3 = [](int k) { return (k + 6) % 3; };
+  auto zr = [&](int k) { return c.wall_z ? min(max(k, 0), c.nz - 1) : k; };
+  auto beyond = [&](int k) { return c.wall_z && (k < 0 || k >= c.nz); };
+
+  // x-y source node of each phi position this thread stages
+  unsigned psrc[KP];
+#pragma unroll
+  for (int it = 0; it < KP; ++it) {
+    const int k = tid + it * NT;
+    int qx = x0 - 3 + k % PX, qy = y0 - 3 + k / PX;
+    if (!inner) {
+      qx = fold3(qx, c.nx, c.wall_x);
+      qy = fold3(qy, c.ny, c.wall_y);
+    }
+    psrc[it] = k < T::NP ? (unsigned)(qx + c.nx * qy) : 0u;
+  }
+  // u, p positions of this thread: its own node, then ring positions (top
+  // row, bottom row, then the two side columns row by row).  upos: the
+  // position; ust: the position whose stencils it takes (its mirror beyond
+  // a wall); usrc: x-y offset of the node whose moments it takes.
+  int upos[KU], ust[KU];
+  unsigned usrc[KU];
+  bool uon[KU];
+#pragma unroll
+  for (int q = 0; q < KU; ++q) {
+    const int r = tid + (q - 1) * NT;
+    int ux = 0, uy = 0;
+    uon[q] = q == 0 || r < NRING;
+    if (q == 0) {
+      ux = lx + 1;
+      uy = ly + 1;
+    } else if (r < UX) {
+      ux = r;
+    } else if (r < 2 * UX) {
+      ux = r - UX;
+      uy = UY - 1;
+    } else if (r < NRING) {
+      const int w = r - 2 * UX;
+      ux = (w & 1) ? UX - 1 : 0;
+      uy = 1 + (w >> 1);
+    }
+    upos[q] = ux + UX * uy;
+    int sx = ux, sy = uy, qx = x0 - 1 + ux, qy = y0 - 1 + uy;
+    if (!inner) {
+      sx = mirror_local(sx, x0 - 1, c.nx, c.wall_x, UX);
+      sy = mirror_local(sy, y0 - 1, c.ny, c.wall_y, UY);
+      qx = fold3(qx, c.nx, c.wall_x);
+      qy = fold3(qy, c.ny, c.wall_y);
+    }
+    ust[q] = sx + UX * sy;
+    usrc[q] = (unsigned)(qx + c.nx * qy);
+  }
+
+  float hv[KP];  // phi plane in flight
+  auto load_phi = [&](int k) {
+    const unsigned zo = pln * (unsigned)fold3(k, c.nz, c.wall_z);
+#pragma unroll
+    for (int it = 0; it < KP; ++it)
+      if (tid + it * NT < T::NP) hv[it] = fl.phh[zo + psrc[it]];
+  };
+  auto store_phi = [&](int k) {
+    float* d = L.ph[s4(k)];
+#pragma unroll
+    for (int it = 0; it < KP; ++it)
+      if (tid + it * NT < T::NP) d[tid + it * NT] = hv[it];
+  };
+  float mv[KU][4];  // gbar moments of the u, p positions, one plane ahead
+  auto load_m = [&](int k) {
+    if (beyond(k)) return;
+    const unsigned zo = pln * (unsigned)fold3(k, c.nz, c.wall_z);
+#pragma unroll
+    for (int q = 0; q < KU; ++q) {
+      if (!uon[q]) continue;
+      const unsigned j = zo + usrc[q];
+      mv[q][0] = fl.m0[j];
+      mv[q][1] = fl.m1x[j];
+      mv[q][2] = fl.m1y[j];
+      mv[q][3] = fl.m1z[j];
+    }
+  };
+  // mu at plane k over the tile + 2 (k3_fields_t's mu stage)
+  auto mu_plane = [&](int k) {
+    if (beyond(k)) return;
+    const float* pm = L.ph[s4(k - 1)];
+    const float* p0 = L.ph[s4(k)];
+    const float* pp = L.ph[s4(k + 1)];
+    float* d = L.mu[s3(k)];
+    for (int pos = tid; pos < T::NM; pos += NT) {
+      int mx = pos % MX, my = pos / MX;
+      if (!inner) {
+        mx = mirror_local(mx, x0 - 2, c.nx, c.wall_x, MX);
+        my = mirror_local(my, y0 - 2, c.ny, c.wall_y, MY);
+      }
+      const int pc = (mx + 1) + PX * (my + 1);
+      float v[Q];
+#pragma unroll
+      for (int i = 1; i < Q; ++i)
+        v[i] = (EZ(i) < 0 ? pm : (EZ(i) > 0 ? pp : p0))[pc + EX(i) + PX * EY(i)];
+      const float h0 = p0[pc];
+      d[pos] = lean_mu(c, h0, lean_lap(v, h0));
+    }
+  };
+  // grad phi, lap mu, u and p at plane k over the tile + 1 (k3_fields_t's
+  // own-node stage); the own node's values go to nxt
+  LeanNode nxt{};
+  auto up_plane = [&](int k) {
+    if (beyond(k)) return;
+    float* dp = L.p[s3(k)];
+#pragma unroll
+    for (int q = 0; q < KU; ++q) {
+      if (!uon[q]) continue;
+      const int sx = ust[q] % UX, sy = ust[q] / UX;
+      const int pc = (sx + 2) + PX * (sy + 2), mc = (sx + 1) + MX * (sy + 1);
+      float v[Q], g[3];
+#pragma unroll
+      for (int i = 1; i < Q; ++i) v[i] = L.ph[s4(k + EZ(i))][pc + EX(i) + PX * EY(i)];
+      lean_grad(v, g[0], g[1], g[2]);
+      const float ph = L.ph[s4(k)][pc];
+      const float mu = L.mu[s3(k)][mc];
+      float lmu = 0.0f;
+      if (c.corr != 0.0f) {
+#pragma unroll
+        for (int i = 1; i < Q; ++i) v[i] = L.mu[s3(zr(k + EZ(i)))][mc + EX(i) + MX * EY(i)];
+        lmu = lean_lap(v, mu);
+      }
+      const float cc = c.corr * lmu;
+      const LeanUP r =
+          lean_recover(c, ph, mu, g[0], g[1], g[2], cc, mv[q][0], mv[q][1], mv[q][2], mv[q][3]);
+      dp[upos[q]] = r.p;
+      if (q == 0) {
+        nxt.ph = ph;
+        nxt.mu = mu;
+        nxt.cc = cc;
+        nxt.p = r.p;
+        nxt.ux = r.ux;
+        nxt.uy = r.uy;
+        nxt.uz = r.uz;
+        nxt.gx = g[0];
+        nxt.gy = g[1];
+        nxt.gz = g[2];
+      }
+    }
+  };
+
+  // prologue: phi(za - 3) and phi(za - 2) staged, phi(za - 1) in flight; the
+  // first four iterations only fill the rings
+  load_phi(za - 3);
+  store_phi(za - 3);
+  load_phi(za - 2);
+  store_phi(za - 2);
+  load_phi(za - 1);
+  const int uc = (lx + 1) + UX * (ly + 1);
+  for (int z = za - 4; z < zb; ++z) {
+    // the own node's pulled populations for the collision of plane z, issued
+    // first so that they arrive while the stages run
+    const bool coll = own && z >= za;
+    const unsigned idx = (unsigned)(gx + c.nx * (gy + c.ny * z));
+    uint16_t fh[Q], gh[Q + 1];
+    if (coll) {
+      const Node3 nd(c, gx, gy, z);
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        if (i > 0) fh[i] = gload<uint16_t>(src, pull3<S, false>(c, nd, i));
+        gh[i] = gload<uint16_t>(src, pull3<S, true>(c, nd, i));
+      }
+    }
+    store_phi(z + 3);
+    if (z + 4 <= zb + 2) load_phi(z + 4);
+    __syncthreads();
+    if (z + 2 >= za - 2) mu_plane(z + 2);
+    __syncthreads();
+    const LeanNode cur = nxt;  // the own node's fields at plane z
+    if (z + 1 >= za - 1) up_plane(z + 1);
+    if (z + 2 >= za - 1 && z + 2 <= zb) load_m(z + 2);
+    __syncthreads();
+    if (coll) {
+      gh[Q] = 0;
+      uint32_t Fr[10], Gr[10];
+      Fr[0] = 0u;
+#pragma unroll
+      for (int j = 1; j <= 9; ++j) Fr[j] = pack16(fh[PI(j)], fh[PI(j) + 1]);
+#pragma unroll
+      for (int k = 0; k < 10; ++k) Gr[k] = pack16(gh[2 * k], gh[2 * k + 1]);
+      float v[Q], gp[3];
+#pragma unroll
+      for (int i = 1; i < Q; ++i) v[i] = L.p[s3(zr(z + EZ(i)))][uc + EX(i) + UX * EY(i)];
+      lean_grad(v, gp[0], gp[1], gp[2]);
+      uint32_t og[10], of[10];
+      const float f0 = lean_collide<S>(c, cur, gp[0], gp[1], gp[2], Gr, Fr, og, of,
+                                       sr_node_key(skey, idx));
+      store_lean<S>(c, dst, idx, f0, og, of);
+    }
+  }
+}
+
 // ---- fused step: one x-y tile of the grid marching up a chunk of z planes
 //
 // A workgroup owns a TX x TY tile of the x-y plane and the planes [za, zb) of
@@ -1300,12 +1558,16 @@ k3_init(CaseDev c, int parity, const double* __restrict__ phi0, const double* __
 // the fused step, by its x-y tile and z chunk (tz planes); the 64-wide tiles
 // give the 16-bit step one 128-byte line per row and plane.  All give the same
 // bits, in every model and storage layout.
-const TileShape kD3Q19Tiles[] = {{16, 8, 4, 512, 0},  {32, 4, 4, 512, 0},  {32, 8, 2, 512, 0},
-                                 {16, 16, 2, 512, 0}, {8, 8, 8, 512, 0},   {32, 8, 16, 256, 0},
-                                 {32, 8, 32, 256, 0}, {32, 16, 16, 512, 0}, {32, 16, 32, 512, 0},
-                                 {32, 8, 64, 256, 0}, {32, 16, 64, 512, 0}, {64, 8, 32, 512, 0},
-                                 {64, 8, 64, 512, 0}};
-constexpr int kD3Q19Fused = 5;  // first fused variant
+const TileShape kD3Q19Tiles[] = {
+    {16, 8, 4, 512, 0, FORM_THREE},  {32, 4, 4, 512, 0, FORM_THREE},
+    {32, 8, 2, 512, 0, FORM_THREE},  {16, 16, 2, 512, 0, FORM_THREE},
+    {8, 8, 8, 512, 0, FORM_THREE},   {32, 8, 16, 256, 0, FORM_FUSED},
+    {32, 8, 32, 256, 0, FORM_FUSED}, {32, 16, 16, 512, 0, FORM_FUSED},
+    {32, 16, 32, 512, 0, FORM_FUSED}, {32, 8, 64, 256, 0, FORM_FUSED},
+    {32, 16, 64, 512, 0, FORM_FUSED}, {64, 8, 32, 512, 0, FORM_FUSED},
+    {64, 8, 64, 512, 0, FORM_FUSED}, {64, 4, 16, 256, 0, FORM_TWO},
+    {64, 4, 22, 256, 0, FORM_TWO},   {64, 4, 43, 256, 0, FORM_TWO},
+    {128, 2, 16, 256, 0, FORM_TWO}};
 const int kD3Q19TileCount = sizeof(kD3Q19Tiles) / sizeof(kD3Q19Tiles[0]);
 
 namespace {
@@ -1354,10 +1616,35 @@ void launch_slab(const CaseDev& c, int parity, int zs, hipStream_t s) {
                        dim3(TX * TY), 0, s, c, parity, zs);
 }
 
+// The second kernel of the two-kernel step (16-bit storage).
+template <int S, int TX, int TY>
+void launch_fcm(const CaseDev& c, int parity, const d3q19::Fields3& fl, int zc, hipStream_t s) {
+  const int ft = ((c.nx + TX - 1) / TX) * ((c.ny + TY - 1) / TY) * ((c.nz + zc - 1) / zc);
+  hipLaunchKernelGGL((d3q19::k3_fcm<S, TX, TY>), dim3(8 * ((ft + 7) / 8)), dim3(TX * TY), 0, s,
+                     c, parity, fl, zc);
+}
+
 template <int S>
 hipError_t pipeline(int variant, const CaseDev& c, int parity, const d3q19::Fields3& fl,
                     int dump, bool collide, hipStream_t s) {
-  if (variant >= kD3Q19Fused && variant < kD3Q19TileCount) {
+  const int form = variant >= 0 && variant < kD3Q19TileCount ? kD3Q19Tiles[variant].form : -1;
+  if (form == FORM_TWO) {
+    // 16-bit storage without the correction from data; otherwise (and for a
+    // field dump) the three-kernel step
+    if constexpr (S != ST_FP32) {
+      if (collide && !dump && !c.phiv) {
+        const TileShape& t = kD3Q19Tiles[variant];
+        const d3q19::RowGrid rg = d3q19::row_grid(c);
+        if (rg.grid.y > 65535u) return hipErrorInvalidConfiguration;
+        hipLaunchKernelGGL(d3q19::k3_pull<S>, rg.grid, rg.block, 0, s, c, parity, fl);
+        if (t.tx == 64) launch_fcm<S, 64, 4>(c, parity, fl, t.tz, s);
+        else launch_fcm<S, 128, 2>(c, parity, fl, t.tz, s);
+        return hipGetLastError();
+      }
+    }
+    variant = 1;
+  }
+  if (form == FORM_FUSED) {
     // 16-bit storage with the correction from data, or on a grid of odd
     // width (the fused 16-bit step pairs x-adjacent nodes), runs the
     // three-kernel step

@@ -871,6 +871,16 @@ int lbm_variant_info(int32_t lattice, int32_t variant, int32_t* tx, int32_t* ty,
   return LBM_OK;
 }
 
+int lbm_variant_form(int32_t lattice, int32_t variant, int32_t* form) {
+  int n;
+  if (!form) return fail(LBM_ERR_ARG, "NULL form");
+  if (lattice != LBM_D2Q9 && lattice != LBM_D3Q19) return fail(LBM_ERR_ARG, "bad lattice");
+  const lbm::TileShape* t = tiles_for(lattice, &n);
+  if (variant < 0 || variant >= n) return fail(LBM_ERR_ARG, "variant out of range");
+  *form = t[variant].form;
+  return LBM_OK;
+}
+
 int lbm_set_launch(lbm_handle* h, int32_t variant, int32_t grid_blocks, int32_t graph_steps) {
   if (!h) return fail(LBM_ERR_ARG, "NULL handle");
   int n;

@@ -75,7 +75,24 @@ def test_required_bytes_grows_with_storage(L):
 
 def test_variants_listed(L):
     v = B.variants(B.D2Q9)
-    assert len(v) >= 2 and all(t[2] == 1 for t in v)
+    assert len(v) >= 2 and all(t[2] == 1 and t[4] == 0 for t in v)
+
+
+def test_variant_forms(L):
+    """Every D3Q19 step form is compiled; the three-kernel variants name a
+    fields tile below 16 planes, the marching forms a z chunk of 16 or more;
+    bad arguments are rejected."""
+    v = B.variants(B.D3Q19)
+    forms = {t[4] for t in v}
+    assert forms == {B.FORM_THREE, B.FORM_FUSED, B.FORM_TWO}
+    assert v[1][4] == B.FORM_THREE
+    assert all((t[2] < 16) == (t[4] == B.FORM_THREE) for t in v)
+    assert all(t[0] * t[1] == t[3] for t in v if t[4] != B.FORM_THREE)
+    f = C.c_int32()
+    assert L.lbm_variant_form(B.D3Q19, len(v), C.byref(f)) == B.ERR_ARG
+    assert L.lbm_variant_form(B.D3Q19, -1, C.byref(f)) == B.ERR_ARG
+    assert L.lbm_variant_form(7, 0, C.byref(f)) == B.ERR_ARG
+    assert L.lbm_variant_form(B.D3Q19, 0, None) == B.ERR_ARG
 
 
 def test_correction_modes_not_mixed(L):

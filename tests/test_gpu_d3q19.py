@@ -140,8 +140,10 @@ def test_splash3d_fp16_against_fp32_5000_steps(hip):
 
 
 def _fused_variants(hip):
-    # the fused variants: an x-y tile with a z chunk of 16 or more planes
-    return [v for v, t in enumerate(hip.variants(hip.D3Q19)) if t[2] >= 16]
+    # the marching variants: the fused step, and the two-kernel step whose
+    # second kernel marches (16-bit storage; otherwise the three-kernel step)
+    return [v for v, t in enumerate(hip.variants(hip.D3Q19))
+            if t[4] in (hip.FORM_FUSED, hip.FORM_TWO)]
 
 
 @pytest.mark.parametrize("dims,wall", [((70, 40, 70), (0, 0, 1)), ((66, 36, 40), (1, 1, 1)),
@@ -151,7 +153,8 @@ def _fused_variants(hip):
                                              ("fp32", 1, 1), ("fp16", 1, 1), ("fp16", 0, 1),
                                              ("fp32", 2, 0), ("fp16", 2, 0)])
 def test_fused_step_bitwise(hip, dims, wall, storage, rf, well):
-    """The fused step (one x-y tile marching up a z chunk) against the
+    """The fused step (one x-y tile marching up a z chunk) and the two-kernel
+    step (pull, then fields and collision marching up z chunks) against the
     three-kernel step: several x and y tiles, several z chunks, ragged edges,
     walls and periodic seams on every axis; the three models (F_a kept, removed
     by Eq. 5, removed by the rate from the data), the three storage layouts and
@@ -169,7 +172,8 @@ def test_fused_step_bitwise(hip, dims, wall, storage, rf, well):
     want = ref.get_state()
     ref.close()
     fused = _fused_variants(hip)
-    assert len(fused) >= 2
+    forms = {hip.variants(hip.D3Q19)[v][4] for v in fused}
+    assert len(fused) >= 2 and forms == {hip.FORM_FUSED, hip.FORM_TWO}
     for v in fused:
         sim = hip.Simulation([case], storage=storage)
         sim.set_launch(v, 0, 16)
@@ -178,17 +182,20 @@ def test_fused_step_bitwise(hip, dims, wall, storage, rf, well):
         sim.close()
 
 
-def test_fused_step_bitwise_splash3d(hip):
-    """The 256x256x128 splash, corrected model, FP32: 20 steps of the fused
-    step equal 20 steps of the three-kernel step, for every fused variant."""
+@pytest.mark.parametrize("storage", ["fp32", "fp16"])
+def test_fused_step_bitwise_splash3d(hip, storage):
+    """The 256x256x128 splash, corrected model: 20 steps of the fused and of
+    the two-kernel step equal 20 steps of the three-kernel step, for every
+    marching variant (with FP32 storage the two-kernel variants run the
+    three-kernel step)."""
     case = W.splash_3d(remove_fa=1)
-    ref = hip.Simulation([case])
+    ref = hip.Simulation([case], storage=storage)
     ref.set_launch(1, 0, 16)
     ref.step(20)
     want = ref.get_state()
     ref.close()
     for v in _fused_variants(hip):
-        sim = hip.Simulation([case])
+        sim = hip.Simulation([case], storage=storage)
         sim.set_launch(v, 0, 16)
         sim.step(20)
         assert np.array_equal(sim.get_state(), want), f"variant {v} differs"

@@ -702,8 +702,11 @@ struct FcmLds {
   float p[3][NU];
 };
 
+// 64-wide tiles ask for 3 waves per SIMD (at most 168 VGPRs): BF16 decoding
+// otherwise needs one register more and runs at 2
 template <int S, int TX, int TY>
-__global__ void __launch_bounds__(TX * TY) k3_fcm(CaseDev c, int parity, Fields3 fl, int zc) {
+__global__ void __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(TX == 64 ? 3 : 1)))
+k3_fcm(CaseDev c, int parity, Fields3 fl, int zc) {
   static_assert(S != ST_FP32, "the lean arithmetic of 16-bit storage");
   using T = FcmLds<TX, TY>;
   constexpr int NT = TX * TY, PX = T::PX, MX = T::MX, MY = T::MY, UX = T::UX, UY = T::UY;

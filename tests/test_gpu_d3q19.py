@@ -202,11 +202,13 @@ def test_fused_step_bitwise_splash3d(hip, storage):
         sim.close()
 
 
-@pytest.mark.parametrize("variant", [1, 10])
-def test_d3q19_batched_equals_single(hip, variant):
+@pytest.mark.parametrize("variant,storage", [(1, "fp32"), (10, "fp32"), (1, "fp16"),
+                                             (12, "fp16"), (15, "fp16"), (16, "bf16")])
+def test_d3q19_batched_equals_single(hip, variant, storage):
     """Three D3Q19 cases of different sizes, wall sets and models in one
     handle (launched in turn every step): each matches its own single-case run
-    to the bit, for a three-kernel and a fused variant."""
+    to the bit, for the three-kernel, the fused and (16-bit) the two-kernel
+    step."""
     cases = []
     for k, (dims, wall, rf) in enumerate([((40, 20, 36), (0, 0, 1), 1),
                                           ((20, 18, 16), (1, 1, 1), 0),
@@ -218,11 +220,11 @@ def test_d3q19_batched_equals_single(hip, variant):
         phi, u, p = W.droplet_fields(prm, (nx * 0.45, ny * 0.5, nz * 0.55), min(dims) * 0.3,
                                      impact_u=0.02, noise=rng.normal(0, 1e-3, (3, nx * ny * nz)))
         cases.append(W.Case(prm, phi, u, p))
-    batch = hip.Simulation(cases)
+    batch = hip.Simulation(cases, storage=storage)
     batch.set_launch(variant, 0, 16)
     batch.step(30)
     for k, case in enumerate(cases):
-        single = hip.Simulation([case])
+        single = hip.Simulation([case], storage=storage)
         single.set_launch(variant, 0, 16)
         single.step(30)
         assert np.array_equal(batch.get_state(k), single.get_state(0)), (variant, k)

@@ -139,8 +139,9 @@ def kernel_name(hip, dim, variant, params, storage):
         return "k_tile (fused D2Q9 step)"
     form = hip.variants(hip.D3Q19)[variant][4]
     rf = params["remove_fa"]
-    if form == hip.FORM_TWO and storage != "fp32" and rf != 2:
-        return "k3_pull + k3_fcm (two-kernel D3Q19 step, 16-bit storage)"
+    if form == hip.FORM_TWO and storage != "fp32":
+        return ("k3_pull + k3_fcm (two-kernel D3Q19 step, 16-bit storage"
+                + (", correction from data)" if rf == 2 else ")"))
     if form != hip.FORM_FUSED:
         return "k3_pull + k3_fields_t + k3_collide"
     coef_zero = rf != 1 or params["theta_m"] == 0.0 or params["rho_l"] == params["rho_g"]

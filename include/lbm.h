@@ -324,9 +324,9 @@ int lbm_variant_info(int32_t lattice, int32_t variant, int32_t* tx, int32_t* ty,
  *   2  two kernels (16-bit storage): the pull, then a tx x ty tile marching up
  *      a chunk of tz planes that forms the fields and collides.
  * Form 1 with 16-bit storage on a grid of odd width or with the correction
- * from data, form 2 with FP32 storage or the correction from data, run the
- * three-kernel step of variant 1.  LBM_ERR_ARG for a NULL form, a bad lattice
- * or a variant out of range. */
+ * from data, and form 2 with FP32 storage, run the three-kernel step of
+ * variant 1.  LBM_ERR_ARG for a NULL form, a bad lattice or a variant out of
+ * range. */
 int lbm_variant_form(int32_t lattice, int32_t variant, int32_t* form);
 
 void lbm_free(lbm_handle* h);

@@ -671,7 +671,7 @@ __global__ void __launch_bounds__(256) k3_collide(CaseDev c, int parity, Fields3
   if (c.phiv) gstore_nt<float>(dst, c.phiv + 4u * idx, n.phh + n.phl);
 }
 
-// ---- 2+3+4 as one march (16-bit storage, no correction from data): k3_fcm
+// ---- 2+3+4 as one march (16-bit storage): k3_fcm
 //
 // The step's second kernel after k3_pull.  A workgroup owns a TX x TY tile
 // of the x-y plane and the planes [za, zb) of one z chunk, and keeps rings of
@@ -692,23 +692,32 @@ __global__ void __launch_bounds__(256) k3_collide(CaseDev c, int parity, Fields3
 // formed around the mirror position with the mirror node's moments, so they
 // equal the mirror node's values; along z the planes beyond a wall are not
 // formed and their reads go to the mirror plane.
-template <int TX, int TY>
+//
+// RF2 (correction from data): the mu stage also forms rho u_o, the
+// uncorrected recovery, over the tile + 2 (a ring of 3 planes, from the
+// gbar moment planes), and the u, p stage takes as the coefficient of -F_a
+// the rate D = drho (phi - phi^(n-1)) + div(rho u_o), with phi^(n-1) from the
+// phi plane of the source copy, as k3_fields_t does; the collision writes
+// phi to the phi plane of the destination copy, as k3_collide does.
+template <int TX, int TY, bool RF2>
 struct FcmLds {
   static constexpr int PX = TX + 6, PY = TY + 6, NP = PX * PY;  // phi, tile + 3
   static constexpr int MX = TX + 4, MY = TY + 4, NM = MX * MY;  // mu, tile + 2
   static constexpr int UX = TX + 2, UY = TY + 2, NU = UX * UY;  // p, tile + 1
+  static constexpr int NQ = RF2 ? NM : 1;
   float ph[4][NP];
   float mu[3][NM];
   float p[3][NU];
+  float q[3][3][NQ];  // RF2: rho u_o, plane slot x component
 };
 
 // 64-wide tiles ask for 3 waves per SIMD (at most 168 VGPRs): BF16 decoding
 // otherwise needs one register more and runs at 2
-template <int S, int TX, int TY>
+template <int S, int TX, int TY, bool RF2>
 __global__ void __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(TX == 64 ? 3 : 1)))
 k3_fcm(CaseDev c, int parity, Fields3 fl, int zc) {
   static_assert(S != ST_FP32, "the lean arithmetic of 16-bit storage");
-  using T = FcmLds<TX, TY>;
+  using T = FcmLds<TX, TY, RF2>;
   constexpr int NT = TX * TY, PX = T::PX, MX = T::MX, MY = T::MY, UX = T::UX, UY = T::UY;
   constexpr int KP = (T::NP + NT - 1) / NT;      // phi positions per thread (at most)
   constexpr int NRING = T::NU - NT;              // u, p positions outside the tile
@@ -802,6 +811,7 @@ k3_fcm(CaseDev c, int parity, Fields3 fl, int zc) {
       if (tid + it * NT < T::NP) d[tid + it * NT] = hv[it];
   };
   float mv[KU][4];  // gbar moments of the u, p positions, one plane ahead
+  float pv[KU];     // RF2: phi^(n-1) of the u, p positions, one plane ahead
   auto load_m = [&](int k) {
     if (beyond(k)) return;
     const unsigned zo = pln * (unsigned)fold3(k, c.nz, c.wall_z);
@@ -813,6 +823,7 @@ k3_fcm(CaseDev c, int parity, Fields3 fl, int zc) {
       mv[q][1] = fl.m1x[j];
       mv[q][2] = fl.m1y[j];
       mv[q][3] = fl.m1z[j];
+      if constexpr (RF2) pv[q] = gload<float>(src, c.phiv + 4u * j);
     }
   };
   // mu at plane k over the tile + 2 (k3_fields_t's mu stage)
@@ -822,8 +833,11 @@ k3_fcm(CaseDev c, int parity, Fields3 fl, int zc) {
     const float* p0 = L.ph[s4(k)];
     const float* pp = L.ph[s4(k + 1)];
     float* d = L.mu[s3(k)];
+    const unsigned zo = RF2 ? pln * (unsigned)fold3(k, c.nz, c.wall_z) : 0u;
     for (int pos = tid; pos < T::NM; pos += NT) {
       int mx = pos % MX, my = pos / MX;
+      // RF2: the node whose moments the position takes (mirror beyond a wall)
+      int qx = x0 - 2 + mx, qy = y0 - 2 + my;
       if (!inner) {
         mx = mirror_local(mx, x0 - 2, c.nx, c.wall_x, MX);
         my = mirror_local(my, y0 - 2, c.ny, c.wall_y, MY);
@@ -834,7 +848,20 @@ k3_fcm(CaseDev c, int parity, Fields3 fl, int zc) {
       for (int i = 1; i < Q; ++i)
         v[i] = (EZ(i) < 0 ? pm : (EZ(i) > 0 ? pp : p0))[pc + EX(i) + PX * EY(i)];
       const float h0 = p0[pc];
-      d[pos] = lean_mu(c, h0, lean_lap(v, h0));
+      const float mu = lean_mu(c, h0, lean_lap(v, h0));
+      d[pos] = mu;
+      if constexpr (RF2) {
+        // rho u_o at the position (k3_fields_t's RF2 stage)
+        if (!inner) {
+          qx = fold3(qx, c.nx, c.wall_x);
+          qy = fold3(qy, c.ny, c.wall_y);
+        }
+        const unsigned j = zo + (unsigned)(qx + c.nx * qy);
+        float g[3];
+        lean_grad(v, g[0], g[1], g[2]);
+        lean_rho_uo(c, h0, mu, g[0], g[1], g[2], fl.m1x[j], fl.m1y[j], fl.m1z[j],
+                    L.q[s3(k)][0][pos], L.q[s3(k)][1][pos], L.q[s3(k)][2][pos]);
+      }
     }
   };
   // grad phi, lap mu, u and p at plane k over the tile + 1 (k3_fields_t's
@@ -854,13 +881,27 @@ k3_fcm(CaseDev c, int parity, Fields3 fl, int zc) {
       lean_grad(v, g[0], g[1], g[2]);
       const float ph = L.ph[s4(k)][pc];
       const float mu = L.mu[s3(k)][mc];
-      float lmu = 0.0f;
-      if (c.corr != 0.0f) {
+      float cc;
+      if constexpr (RF2) {
+        // D = drho (phi - phi^(n-1)) + div(rho u_o) (k3_fields_t's RF2 rate)
+        float qx[Q], qy[Q], qz[Q];
 #pragma unroll
-        for (int i = 1; i < Q; ++i) v[i] = L.mu[s3(zr(k + EZ(i)))][mc + EX(i) + MX * EY(i)];
-        lmu = lean_lap(v, mu);
+        for (int i = 1; i < Q; ++i) {
+          const int sl = s3(zr(k + EZ(i))), o = mc + EX(i) + MX * EY(i);
+          qx[i] = L.q[sl][0][o];
+          qy[i] = L.q[sl][1][o];
+          qz[i] = L.q[sl][2][o];
+        }
+        cc = __builtin_fmaf(ph - pv[q], c.drho, lean_div(qx, qy, qz));
+      } else {
+        float lmu = 0.0f;
+        if (c.corr != 0.0f) {
+#pragma unroll
+          for (int i = 1; i < Q; ++i) v[i] = L.mu[s3(zr(k + EZ(i)))][mc + EX(i) + MX * EY(i)];
+          lmu = lean_lap(v, mu);
+        }
+        cc = c.corr * lmu;
       }
-      const float cc = c.corr * lmu;
       const LeanUP r =
           lean_recover(c, ph, mu, g[0], g[1], g[2], cc, mv[q][0], mv[q][1], mv[q][2], mv[q][3]);
       dp[upos[q]] = r.p;
@@ -926,6 +967,8 @@ k3_fcm(CaseDev c, int parity, Fields3 fl, int zc) {
       const float f0 = lean_collide<S>(c, cur, gp[0], gp[1], gp[2], Gr, Fr, og, of,
                                        sr_node_key(skey, idx));
       store_lean<S>(c, dst, idx, f0, og, of);
+      // correction from data: the copy carries this step's phi
+      if constexpr (RF2) gstore_nt<float>(dst, c.phiv + 4u * idx, cur.ph);
     }
   }
 }
@@ -1623,8 +1666,12 @@ void launch_slab(const CaseDev& c, int parity, int zs, hipStream_t s) {
 template <int S, int TX, int TY>
 void launch_fcm(const CaseDev& c, int parity, const d3q19::Fields3& fl, int zc, hipStream_t s) {
   const int ft = ((c.nx + TX - 1) / TX) * ((c.ny + TY - 1) / TY) * ((c.nz + zc - 1) / zc);
-  hipLaunchKernelGGL((d3q19::k3_fcm<S, TX, TY>), dim3(8 * ((ft + 7) / 8)), dim3(TX * TY), 0, s,
-                     c, parity, fl, zc);
+  if (c.phiv)
+    hipLaunchKernelGGL((d3q19::k3_fcm<S, TX, TY, true>), dim3(8 * ((ft + 7) / 8)),
+                       dim3(TX * TY), 0, s, c, parity, fl, zc);
+  else
+    hipLaunchKernelGGL((d3q19::k3_fcm<S, TX, TY, false>), dim3(8 * ((ft + 7) / 8)),
+                       dim3(TX * TY), 0, s, c, parity, fl, zc);
 }
 
 template <int S>
@@ -1632,10 +1679,10 @@ hipError_t pipeline(int variant, const CaseDev& c, int parity, const d3q19::Fiel
                     int dump, bool collide, hipStream_t s) {
   const int form = variant >= 0 && variant < kD3Q19TileCount ? kD3Q19Tiles[variant].form : -1;
   if (form == FORM_TWO) {
-    // 16-bit storage without the correction from data; otherwise (and for a
-    // field dump) the three-kernel step
+    // 16-bit storage; FP32 storage (and a field dump) runs the three-kernel
+    // step
     if constexpr (S != ST_FP32) {
-      if (collide && !dump && !c.phiv) {
+      if (collide && !dump) {
         const TileShape& t = kD3Q19Tiles[variant];
         const d3q19::RowGrid rg = d3q19::row_grid(c);
         if (rg.grid.y > 65535u) return hipErrorInvalidConfiguration;

@@ -17,9 +17,9 @@ struct TileShape {
 
 // D3Q19 step forms.  THREE: k3_pull, k3_fields_t on tx x ty x tz tiles,
 // k3_collide.  FUSED: one kernel, a tx x ty tile of the x-y plane marching
-// up a chunk of tz planes.  TWO (16-bit storage): k3_pull, then k3_fcm, a tx
-// x ty tile marching up a chunk of tz planes that forms the fields and
-// collides.
+// up a chunk of tz planes.  TWO (16-bit storage, every model): k3_pull, then
+// k3_fcm, a tx x ty tile marching up a chunk of tz planes that forms the
+// fields and collides.
 enum TileForm { FORM_THREE = 0, FORM_FUSED = 1, FORM_TWO = 2 };
 
 // Everything one step / field launch needs.

@@ -141,7 +141,7 @@ def test_splash3d_fp16_against_fp32_5000_steps(hip):
 
 def _fused_variants(hip):
     # the marching variants: the fused step, and the two-kernel step whose
-    # second kernel marches (16-bit storage; otherwise the three-kernel step)
+    # second kernel marches (16-bit storage; with FP32 the three-kernel step)
     return [v for v, t in enumerate(hip.variants(hip.D3Q19))
             if t[4] in (hip.FORM_FUSED, hip.FORM_TWO)]
 

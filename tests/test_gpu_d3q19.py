@@ -151,7 +151,7 @@ def _fused_variants(hip):
 @pytest.mark.parametrize("storage,rf,well", [("fp32", 1, 0), ("fp16", 1, 0), ("bf16", 1, 0),
                                              ("fp32", 0, 0), ("fp16", 0, 0), ("bf16", 0, 0),
                                              ("fp32", 1, 1), ("fp16", 1, 1), ("fp16", 0, 1),
-                                             ("fp32", 2, 0), ("fp16", 2, 0)])
+                                             ("fp32", 2, 0), ("fp16", 2, 0), ("bf16", 2, 0)])
 def test_fused_step_bitwise(hip, dims, wall, storage, rf, well):
     """The fused step (one x-y tile marching up a z chunk) and the two-kernel
     step (pull, then fields and collision marching up z chunks) against the

@@ -77,11 +77,24 @@ __device__ __forceinline__ void pull_moments(const CaseDev& c, const char* src, 
 }
 
 // ---- 1: pull, phi, moments
+// One grid row (y, z) per blockIdx.x.  zc = 0: rows in storage order.  zc > 0
+// (ahead of k3_fcm on chunks of zc planes): the planes go offset-major
+// through the chunks, from the last plane of every chunk down to the first,
+// so that the first planes of each chunk -- the ones k3_fcm pulls first --
+// are read last and are still in the Infinity Cache when k3_fcm starts;
+// blockIdx.x then spans ny x zc x (number of chunks) rows, and the rows of
+// planes beyond the grid exit.
 template <int S>
-__global__ void __launch_bounds__(256) k3_pull(CaseDev c, int parity, Fields3 fl) {
+__global__ void __launch_bounds__(256) k3_pull(CaseDev c, int parity, Fields3 fl, int zc) {
   const int x = blockIdx.y * blockDim.x + threadIdx.x;
   if (x >= c.nx) return;
-  const Node3 nd(c, x, blockIdx.x);
+  int z = blockIdx.x / c.ny;
+  if (zc > 0) {
+    const int nch = (c.nz + zc - 1) / zc;
+    z = (z % nch) * zc + (zc - 1 - z / nch);
+    if (z >= c.nz) return;
+  }
+  const Node3 nd(c, x, blockIdx.x % c.ny, z);
   const unsigned idx = nd.idx;
   const char* src = parity ? c.state[1] : c.state[0];
   float hi, lo, m0, mx, my, mz;
@@ -1684,9 +1697,10 @@ hipError_t pipeline(int variant, const CaseDev& c, int parity, const d3q19::Fiel
     if constexpr (S != ST_FP32) {
       if (collide && !dump) {
         const TileShape& t = kD3Q19Tiles[variant];
-        const d3q19::RowGrid rg = d3q19::row_grid(c);
+        d3q19::RowGrid rg = d3q19::row_grid(c);
         if (rg.grid.y > 65535u) return hipErrorInvalidConfiguration;
-        hipLaunchKernelGGL(d3q19::k3_pull<S>, rg.grid, rg.block, 0, s, c, parity, fl);
+        rg.grid.x = (unsigned)(c.ny * t.tz * ((c.nz + t.tz - 1) / t.tz));
+        hipLaunchKernelGGL(d3q19::k3_pull<S>, rg.grid, rg.block, 0, s, c, parity, fl, t.tz);
         if (t.tx == 64) launch_fcm<S, 64, 4>(c, parity, fl, t.tz, s);
         else launch_fcm<S, 128, 2>(c, parity, fl, t.tz, s);
         return hipGetLastError();
@@ -1713,7 +1727,7 @@ hipError_t pipeline(int variant, const CaseDev& c, int parity, const d3q19::Fiel
   }
   const d3q19::RowGrid rg = d3q19::row_grid(c);
   if (rg.grid.y > 65535u) return hipErrorInvalidConfiguration;
-  hipLaunchKernelGGL(d3q19::k3_pull<S>, rg.grid, rg.block, 0, s, c, parity, fl);
+  hipLaunchKernelGGL(d3q19::k3_pull<S>, rg.grid, rg.block, 0, s, c, parity, fl, 0);
   switch (variant) {
     case 0: launch_fields_t<16, 8, 4, (S != ST_FP32)>(c, fl, dump, parity, s); break;
     case 1: launch_fields_t<32, 4, 4, (S != ST_FP32)>(c, fl, dump, parity, s); break;

@@ -934,7 +934,9 @@ hipError_t launch_step_v(const LaunchArgs& a) {
 // height, depth, threads per workgroup (one, two or four nodes per thread) and
 // the strip width of the tile order (0: default).  The last three reuse
 // kernels of earlier entries with 1024-node strips (measured faster on
-// 4096^2 grids; narrower strips were slower).
+// 4096^2 grids; narrower strips were slower).  Variants 8 and 9 also ask for
+// 6 waves per SIMD, which their 512-thread tiles' LDS allows: the 16-bit
+// kernels then fit 80 VGPRs instead of 82-93 (5 waves).
 const TileShape kD2Q9Tiles[] = {
     {32, 16, 1, 512, 0},  {64, 8, 1, 512, 0},    {64, 16, 1, 512, 0},  {128, 8, 1, 512, 0},
     {128, 16, 1, 1024, 0}, {64, 32, 1, 1024, 0}, {64, 8, 1, 256, 0},   {64, 16, 1, 256, 0},
@@ -951,8 +953,8 @@ hipError_t d2q9_step(int variant, const LaunchArgs& a) {
     case 5: return launch_step_v<64, 32, 2, 4>(a);
     case 6: return launch_step_v<64, 8, 2, 4>(a);
     case 7: return launch_step_v<64, 16, 4, 4>(a);
-    case 8: return launch_step_v<64, 16, 2, 4>(a);
-    case 9: return launch_step_v<128, 8, 2, 4>(a);
+    case 8: return launch_step_v<64, 16, 2, 6>(a);
+    case 9: return launch_step_v<128, 8, 2, 6>(a);
     case 10: return launch_step_v<64, 8, 2, 4>(a);
     default: return hipErrorInvalidValue;
   }
